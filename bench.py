@@ -1,0 +1,189 @@
+"""Benchmark: velocity-node updates per second of the half-range
+Gauss-Hermite lattice Boltzmann time step on one MI355X.
+
+Workload (the largest single-GPU configuration): 256 independent channels,
+Nx = 16384 tanh-stretched cells (A = 0.9), HHLB(15;16) (V = 32 momenta),
+WENO-5 + TVD RK-3, f and chi (Dt = 2), Kn ~ U[0.005, 0.05] (PCG64 seed 0),
+g = -1, T_left = 1, T_right = 1.5, CFL 0.5.  One step = one RK-3 step of
+every channel; a node-update is one (x_i, p_k) pair of f and chi advanced
+by one step.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
+--no-cpu-baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+
+N_CH, NX, Q = 256, 16384, 16
+
+
+def workload(n_ch=N_CH, nx=NX):
+    import paper_1708_03249_amd as H
+    from paper_1708_03249_amd.inputs import large_batch_kn
+    kns = large_batch_kn(n_ch, seed=0)
+    return [H.Channel(quad=H.HALF_HERMITE, Q=Q, N=Q - 1, Nx=nx, adv=H.WENO5, transverse_dof=2,
+                      L=1.0, stretch_A=0.9, Kn=kn, g=-1.0, T_left=1.0, T_right=1.5, p0=1.0,
+                      dt=-0.5) for kn in kns]
+
+
+def bytes_per_node_update(nfun=2, word=8):
+    """Algorithmic HBM bytes of one RK-3 step with one kernel per stage:
+    stage 1 reads y^n and writes y1; stages 2 and 3 read the stage state and
+    y^n and write the next state: 8 array passes per function."""
+    return 8 * nfun * word
+
+
+def flops_per_node_update(Q=Q, N=Q - 1, nfun=2, nc=8):
+    """Algorithmic floating-point operations of one node-update (both
+    functions, three stages), counting an FMA as two: WENO-5 face value
+    (3 smoothness indicators, 3 candidates, weights: 58), flux difference and
+    RK combination (6), structured force matrix (half block + rank-1:
+    2(Q+2)), collision (4); per cell and shared by its 2Q nodes: moments
+    (7 per node), equilibrium (2(Q+nc) points x (N+1) recurrence levels x 8
+    flops + 2Q (N+1) x 2 contraction)."""
+    V = 2 * Q
+    per_node_fn = 58 + 6 + 2 * (Q + 2) + 4
+    per_cell = 7 * V + 2 * (Q + nc) * (N + 1) * 8 + V * (N + 1) * 2
+    return 3 * (nfun * per_node_fn + per_cell / V)
+
+
+def cpu_baseline(n_channels, steps):
+    """Time the plain CPU oracle on a bounded sample of the same workload:
+    n_channels channels (one thread each) for `steps` RK-3 steps."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle as O
+    import paper_1708_03249_amd as H
+    chans = workload()[:n_channels]
+    dts = []
+    for ch in chans:
+        oc = O.Channel(quad=O.HALF, Q=Q, N=Q - 1, Nx=NX, adv=O.WENO5, Dt=2, A=0.9, Kn=ch.Kn,
+                       g=-1.0, T_left=1.0, T_right=1.5)
+        dts.append(O.cfl_dt(oc, 0.5))
+
+    def one(c):
+        ch = chans[c]
+        oc = O.Channel(quad=O.HALF, Q=Q, N=Q - 1, Nx=NX, adv=O.WENO5, Dt=2, A=0.9, Kn=ch.Kn,
+                       g=-1.0, T_left=1.0, T_right=1.5, dt=dts[c])
+        f, chi = O.initial_state(oc)
+        O.run(oc, steps, f, chi)
+
+    O.lib()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=n_channels) as ex:
+        list(ex.map(one, range(n_channels)))
+    el = time.perf_counter() - t0
+    nu = n_channels * NX * 2 * Q * steps
+    return {"value": nu / el, "unit": "node-updates/s", "cores": n_channels, "kind": "oracle",
+            "sample": f"{n_channels} of the 256 channels (Nx={NX}, HHLB(15;16), f and chi), "
+                      f"{steps} RK-3 steps each, one thread per channel, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-channels", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "channels are independent and would shard across GPUs without exchange, "
+              "which is not built here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1708_03249_amd as H
+
+    chans = workload()
+    s = H.Solver(chans)
+    s.init_equilibrium(1.0, 0.0, 1.0)
+    print(f"[bench] {len(chans)} channels x Nx={NX}, V={2 * Q}; workspace "
+          f"{s.ws_bytes / 2**30:.2f} GiB; warmup {args.warmup}", file=sys.stderr, flush=True)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    launches, windows = s.launch_info()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    nw, mass, bad = s.diagnostics()
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0, "non-finite populations"
+    mass_err = float((mass - 1.0).abs().max().item())
+    node_updates = sum(c.V * c.Nx for c in chans) * args.steps
+    value = node_updates / (ms / 1e3)
+    # dominant kernel: the fused stage kernel (all launches of the timed region)
+    n_launch = 3 * args.steps * launches
+    avg_launch_s = ms / 1e3 / n_launch
+    nu_per_launch = sum(c.V * c.Nx for c in chans) / launches
+    bpl = bytes_per_node_update() / 3 * nu_per_launch
+    fpl = flops_per_node_update() / 3 * nu_per_launch
+    gbs = bpl / avg_launch_s / 1e9
+    tfs = fpl / avg_launch_s / 1e12
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tfs / FP64_VECTOR_PEAK_TFLOPS
+    if hbm_frac >= alu_frac:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4), "traffic": None}
+        other = {"alu_fp64_tflops": round(tfs, 2), "alu_frac": round(alu_frac, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": None}
+        other = {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4)}
+    roof["kernel"] = "hhlb::stage_kernel<0,16,2,0> (one RK-3 stage, FP64)"
+    roof["avg_launch_us"] = round(avg_launch_s * 1e6, 2)
+    roof.update(other)
+    out = {
+        "metric": "velocity-node updates/s (x·p_x)",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(chans)} channels x Nx={NX} tanh-stretched (A=0.9), "
+                               "HHLB(15;16) V=32, WENO5+RK3, f and chi, Kn~U[0.005,0.05], g=-1, "
+                               "T_right/T_left=1.5, CFL 0.5",
+                   "channels": len(chans), "Nx": NX, "V": 2 * Q, "form": "FP64",
+                   "node_updates_per_step": node_updates // args.steps},
+        "roofline": roof,
+        "mass_drift": mass_err,
+        "wall_s": round(wall, 3),
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu baseline: {args.cpu_channels} channels x {args.cpu_steps} steps",
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_channels, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

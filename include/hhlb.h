@@ -1,0 +1,162 @@
+/*
+ * hhlb.h -- C ABI of the MI355X (gfx950) library for the time step of the
+ * half-range Gauss-Hermite lattice Boltzmann model with a force term
+ * (Ambrus, Sofonea, Fournier, Blanco, arXiv:1708.03249).
+ *
+ * The library advances force-driven 1-D channels between diffuse-reflecting
+ * walls.  Per time step (Sec. IV.C, Eq. rk3, three stages) it takes the
+ * moments n, u, T of the populations f and of the reduced transverse-energy
+ * function chi, builds the truncated half-range equilibrium (Sec. IV.B.3),
+ * applies BGK relaxation with tau = Kn/n (Eq. tau), the force term as the
+ * discrete momentum-derivative matrix with the delta term at p = 0
+ * (Eq. hh_Kk_hh), WENO-5 or third-order upwind advection on a tanh-stretched
+ * grid (Eqs. x_eta, etai, weno5_flux), and the diffuse-reflection closure
+ * with zero net wall mass flux (Eq. nplus_def).
+ *
+ * Conventions: m = 1; F = m g with g the acceleration along x (the paper's
+ * F = -m g_p); walls at x = -L/2 (left, temperature T_left) and x = +L/2
+ * (right, T_right).  Velocity index k < V/2: positive momenta p_k = p0 z_k in
+ * ascending order; k >= V/2: the mirrored p_k = -p_{k-V/2}.
+ * Half-range HHLB(N;Q): V = 2Q.  Full-range HLB(N;Q) (Sec. IV.A, Q even): V = Q.
+ *
+ * Memory: the caller owns every device buffer (allocate them with any
+ * allocator, e.g. torch.empty(..., device="cuda")); the library allocates no
+ * device memory.  The library owns its host-side tables and frees them in
+ * hhlb_destroy.  All device work is enqueued on the HIP stream given to
+ * hhlb_create; outputs are valid once the caller synchronises that stream.
+ *
+ * Errors: every call returns an hhlb_status; no C++ exception crosses the ABI.
+ * Arguments are checked before any side effect (HHLB_E_ARG leaves all state
+ * unchanged).  hhlb_last_error() describes the last failure on this thread.
+ */
+#ifndef HHLB_H
+#define HHLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hhlb_status;
+enum {
+  HHLB_OK = 0,
+  HHLB_E_ARG = -1,          /* invalid argument; nothing was changed          */
+  HHLB_E_UNSUPPORTED = -2,  /* valid model, but no kernel for this shape      */
+  HHLB_E_HIP = -3,          /* a HIP runtime call failed (see last_error)      */
+  HHLB_E_NOMEM = -4,        /* host allocation failed                          */
+  HHLB_E_NUMERIC = -5,      /* table construction lost accuracy                */
+  HHLB_E_STATE = -6         /* call out of order (e.g. no workspace bound)     */
+};
+
+enum { HHLB_HALF_HERMITE = 0, HHLB_FULL_HERMITE = 1 };   /* quadrature kind   */
+enum { HHLB_WENO5 = 0, HHLB_UPWIND3 = 1 };              /* advection scheme  */
+enum { HHLB_FP64 = 0 };                                 /* arithmetic path   */
+
+/* One channel, following the paper's statement of the problem (Sec. IV.D,
+ * Sec. V.A): quadrature kind and order Q, equilibrium order N, grid, Kn,
+ * force, wall temperatures and time step. */
+typedef struct {
+  int32_t quad;            /* HHLB_HALF_HERMITE or HHLB_FULL_HERMITE                 */
+  int32_t Q;               /* quadrature order (nodes per half axis for HHLB)        */
+  int32_t N;               /* equilibrium order, 0 <= N < Q; N < 0 selects min(20,Q-1) */
+  int32_t Nx;              /* number of cells, >= 8                                  */
+  int32_t adv;             /* HHLB_WENO5 or HHLB_UPWIND3                             */
+  int32_t transverse_dof;  /* Dt: 0 (the paper's 1-D gas, chi absent) or 2          */
+  double L;                /* channel width, > 0                                     */
+  double stretch_A;        /* tanh stretching A in [0,1); 0 = uniform cells          */
+  double Kn;               /* Knudsen number > 0; +INFINITY = collisionless          */
+  double g;                /* acceleration along x (F = m g)                         */
+  double T_left, T_right;  /* wall temperatures > 0                                  */
+  double p0;               /* momentum scale > 0                                     */
+  double dt;               /* > 0: time step; < 0: CFL number |dt|, see hhlb_time_steps */
+} hhlb_channel;
+
+typedef struct hhlb_solver hhlb_solver;   /* opaque */
+
+/* ---- host-only tables (FP64, no GPU needed) ------------------------------ */
+
+/* Velocity set of Sec. IV.A.1 / IV.B.1: p_out[V] momenta p_k and w_out[V]
+ * quadrature weights (a mirrored node repeats its weight).  Host pointers,
+ * caller-owned, V entries each (V = 2Q half-range, Q full-range). */
+hhlb_status hhlb_nodes(int32_t quad, int32_t Q, double p0, double *p_out, double *w_out);
+
+/* Discrete momentum-derivative matrix, Eq. (hh_Kk_hh) (half-range) or
+ * Eq. (H_Kk) (full-range): K_out[k*V + k'] (row-major, V*V host doubles),
+ * (d f/d p)_k = sum_k' K[k][k'] f_k'. */
+hhlb_status hhlb_force_matrix(int32_t quad, int32_t Q, double p0, double *K_out);
+
+/* Truncated discrete equilibrium f^eq_k = n g_k(u, T) of order N,
+ * Eq. (hh_gk) / Eq. (H_gk): feq_out[V] host doubles. */
+hhlb_status hhlb_equilibrium(int32_t quad, int32_t Q, int32_t N, double p0, double n, double u,
+                             double T, double *feq_out);
+
+/* ---- solver -------------------------------------------------------------- */
+
+/* Validate n_ch channels and build their tables on the host (extended
+ * precision, rounded to double).  precision must be HHLB_FP64.  hip_stream is
+ * a hipStream_t (NULL = default stream).  *out receives the solver. */
+hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t precision,
+                        void *hip_stream, hhlb_solver **out);
+
+/* Bytes of device workspace the solver needs (tables, grid, three RK
+ * state copies, diagnostics). */
+hhlb_status hhlb_workspace_bytes(const hhlb_solver *s, size_t *bytes);
+
+/* Bind caller-owned device memory of at least hhlb_workspace_bytes bytes,
+ * 256-byte aligned, and upload the tables (synchronises the stream once).
+ * The memory must stay valid until hhlb_destroy or the next bind. */
+hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr);
+
+/* State layout at the boundary: per channel c, V*Nx doubles starting at
+ * off[c] (off has n_ch+1 entries, off[n_ch] = total), node-major
+ * (k = 0..V-1), cell index fastest (i = 0..Nx-1, left to right).  f and chi
+ * use the same layout in separate arrays.  Host pointer. */
+hhlb_status hhlb_state_offsets(const hhlb_solver *s, int64_t *off);
+
+/* The time step of each channel after resolving CFL requests:
+ * dt = min(|cfl| * min_i dx_i / max_k |p_k/m|, Kn/2) when dt < 0 was given
+ * (the Kn/2 cap keeps the stiff BGK term inside RK-3's stability region).
+ * dt_out: n_ch host doubles. */
+hhlb_status hhlb_time_steps(const hhlb_solver *s, double *dt_out);
+
+/* Copy a state in (device pointers, boundary layout, FP64).  chi_dev may be
+ * NULL only if every channel has Dt = 0.  Asynchronous on the stream. */
+hhlb_status hhlb_set_state(hhlb_solver *s, const double *f_dev, const double *chi_dev);
+
+/* Set f_k = n0 g_k(u0, T0) in every cell and chi_k = (Dt/2) T0 f_k. */
+hhlb_status hhlb_init_equilibrium(hhlb_solver *s, double n0, double u0, double T0);
+
+/* Advance every channel by n_steps TVD RK-3 steps (Eq. rk3).  Asynchronous. */
+hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps);
+
+/* Copy the state out (device pointers, boundary layout).  chi_dev may be
+ * NULL.  Asynchronous on the stream. */
+hhlb_status hhlb_get_state(const hhlb_solver *s, double *f_dev, double *chi_dev);
+
+/* Moments of Eq. (fmoms) per cell, with chi's transverse energy in T:
+ * n, u, T as device arrays of sum(Nx) doubles, channels concatenated. */
+hhlb_status hhlb_moments(const hhlb_solver *s, double *n_dev, double *u_dev, double *T_dev);
+
+/* Diagnostics (device pointers, any may be NULL): n_wall_dev[2*c+{0,1}]
+ * wall densities n_+ (left) and n_- (right) of the last evaluated stage,
+ * Eq. (nplus_def); mass_dev[c] = sum_i dx_i n_i (Eq. Ndef); nonfinite_dev[0]
+ * = number of non-finite populations in the state. */
+hhlb_status hhlb_diagnostics(const hhlb_solver *s, double *n_wall_dev, double *mass_dev,
+                             int32_t *nonfinite_dev);
+
+/* Kernel launches one hhlb_step of one RK stage issues (for profiling). */
+hhlb_status hhlb_launch_info(const hhlb_solver *s, int32_t *launches_per_stage,
+                             int64_t *windows_total);
+
+hhlb_status hhlb_destroy(hhlb_solver *s);
+
+/* Text of the last error on this thread ("" if none); valid until the next
+ * call on the same thread. */
+const char *hhlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HHLB_H */

@@ -1,0 +1,236 @@
+"""Python binding of libhhlb.so, the gfx950 library for the time step of the
+half-range Gauss-Hermite lattice Boltzmann model with a force term
+(arXiv:1708.03249).
+
+Argument marshalling only: every arithmetic step of the time step runs in the
+HIP kernels behind ``include/hhlb.h``.  PyTorch provides device memory and
+the stream.  The library must be built (``python -m paper_1708_03249_amd.build``);
+importing this module fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhhlb.so")
+
+HALF_HERMITE, FULL_HERMITE = 0, 1
+WENO5, UPWIND3 = 0, 1
+FP64 = 0
+
+_STATUS = {0: "HHLB_OK", -1: "HHLB_E_ARG", -2: "HHLB_E_UNSUPPORTED", -3: "HHLB_E_HIP",
+           -4: "HHLB_E_NOMEM", -5: "HHLB_E_NUMERIC", -6: "HHLB_E_STATE"}
+
+
+class HHLBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _CChannel(ctypes.Structure):
+    _fields_ = [("quad", ctypes.c_int32), ("Q", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("Nx", ctypes.c_int32), ("adv", ctypes.c_int32),
+                ("transverse_dof", ctypes.c_int32), ("L", ctypes.c_double),
+                ("stretch_A", ctypes.c_double), ("Kn", ctypes.c_double), ("g", ctypes.c_double),
+                ("T_left", ctypes.c_double), ("T_right", ctypes.c_double),
+                ("p0", ctypes.c_double), ("dt", ctypes.c_double)]
+
+
+@dataclass
+class Channel:
+    """A force-driven channel between diffuse walls (see include/hhlb.h)."""
+    quad: int = HALF_HERMITE
+    Q: int = 4
+    N: int = -1
+    Nx: int = 64
+    adv: int = WENO5
+    transverse_dof: int = 2
+    L: float = 1.0
+    stretch_A: float = 0.0
+    Kn: float = 0.1
+    g: float = -0.1
+    T_left: float = 1.0
+    T_right: float = 1.0
+    p0: float = 1.0
+    dt: float = 5e-4
+
+    @property
+    def V(self) -> int:
+        return 2 * self.Q if self.quad == HALF_HERMITE else self.Q
+
+    def _c(self) -> _CChannel:
+        return _CChannel(self.quad, self.Q, self.N, self.Nx, self.adv, self.transverse_dof,
+                         self.L, self.stretch_A, self.Kn, self.g, self.T_left, self.T_right,
+                         self.p0, self.dt)
+
+
+_lib = None
+
+
+def lib():
+    """Load libhhlb.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1708_03249_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        dp, vp = ctypes.POINTER(ctypes.c_double), ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        L.hhlb_last_error.restype = ctypes.c_char_p
+        L.hhlb_nodes.argtypes = [i32, i32, ctypes.c_double, dp, dp]
+        L.hhlb_force_matrix.argtypes = [i32, i32, ctypes.c_double, dp]
+        L.hhlb_equilibrium.argtypes = [i32, i32, i32] + [ctypes.c_double] * 4 + [dp]
+        L.hhlb_create.argtypes = [ctypes.POINTER(_CChannel), i32, i32, vp, ctypes.POINTER(vp)]
+        L.hhlb_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.hhlb_bind_workspace.argtypes = [vp, vp]
+        L.hhlb_state_offsets.argtypes = [vp, ctypes.POINTER(i64)]
+        L.hhlb_time_steps.argtypes = [vp, dp]
+        L.hhlb_set_state.argtypes = [vp, vp, vp]
+        L.hhlb_init_equilibrium.argtypes = [vp] + [ctypes.c_double] * 3
+        L.hhlb_step.argtypes = [vp, i64]
+        L.hhlb_get_state.argtypes = [vp, vp, vp]
+        L.hhlb_moments.argtypes = [vp, vp, vp, vp]
+        L.hhlb_diagnostics.argtypes = [vp, vp, vp, vp]
+        L.hhlb_launch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.hhlb_destroy.argtypes = [vp]
+        for name in ("hhlb_nodes", "hhlb_force_matrix", "hhlb_equilibrium", "hhlb_create",
+                     "hhlb_workspace_bytes", "hhlb_bind_workspace", "hhlb_state_offsets",
+                     "hhlb_time_steps", "hhlb_set_state", "hhlb_init_equilibrium", "hhlb_step",
+                     "hhlb_get_state", "hhlb_moments", "hhlb_diagnostics", "hhlb_launch_info",
+                     "hhlb_destroy"):
+            getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise HHLBError(st, lib().hhlb_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def nodes(quad: int, Q: int, p0: float = 1.0):
+    V = 2 * Q if quad == HALF_HERMITE else Q
+    p, w = np.zeros(V), np.zeros(V)
+    _check(lib().hhlb_nodes(quad, Q, p0, _dptr(p), _dptr(w)))
+    return p, w
+
+
+def force_matrix(quad: int, Q: int, p0: float = 1.0):
+    V = 2 * Q if quad == HALF_HERMITE else Q
+    K = np.zeros((V, V))
+    _check(lib().hhlb_force_matrix(quad, Q, p0, _dptr(K)))
+    return K
+
+
+def equilibrium(quad: int, Q: int, N: int, n: float, u: float, T: float, p0: float = 1.0):
+    V = 2 * Q if quad == HALF_HERMITE else Q
+    g = np.zeros(V)
+    _check(lib().hhlb_equilibrium(quad, Q, N, p0, n, u, T, _dptr(g)))
+    return g
+
+
+class Solver:
+    """Channels advanced on one GPU.  Device memory comes from torch."""
+
+    def __init__(self, channels, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.channels = list(channels)
+        arr = (_CChannel * len(self.channels))(*[c._c() for c in self.channels])
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().hhlb_create(arr, len(self.channels), FP64,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        nb = ctypes.c_size_t()
+        _check(lib().hhlb_workspace_bytes(self.h, ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        _check(lib().hhlb_bind_workspace(self.h, ctypes.c_void_p(self._ws_ptr)))
+        off = (ctypes.c_int64 * (len(self.channels) + 1))()
+        _check(lib().hhlb_state_offsets(self.h, off))
+        self.offsets = np.array(off[:], dtype=np.int64)
+        dts = np.zeros(len(self.channels))
+        _check(lib().hhlb_time_steps(self.h, _dptr(dts)))
+        self.dt = dts
+        self.has_chi = any(c.transverse_dof > 0 for c in self.channels)
+        self.total = int(self.offsets[-1])
+        self.cells = np.cumsum([0] + [c.Nx for c in self.channels])
+
+    # -- state ------------------------------------------------------------
+    def set_state(self, f, chi=None):
+        f = f.contiguous()
+        chi = chi.contiguous() if chi is not None else None
+        assert f.dtype == self.torch.float64 and f.numel() == self.total
+        _check(lib().hhlb_set_state(self.h, ctypes.c_void_p(f.data_ptr()),
+                                    ctypes.c_void_p(chi.data_ptr() if chi is not None else 0)))
+
+    def init_equilibrium(self, n0=1.0, u0=0.0, T0=1.0):
+        _check(lib().hhlb_init_equilibrium(self.h, n0, u0, T0))
+
+    def get_state(self):
+        t = self.torch
+        f = t.empty(self.total, dtype=t.float64, device=self.device)
+        c = t.empty(self.total, dtype=t.float64, device=self.device)
+        _check(lib().hhlb_get_state(self.h, ctypes.c_void_p(f.data_ptr()),
+                                    ctypes.c_void_p(c.data_ptr())))
+        return f, c
+
+    def step(self, n_steps: int):
+        _check(lib().hhlb_step(self.h, int(n_steps)))
+
+    def moments(self):
+        t = self.torch
+        nc = int(self.cells[-1])
+        n, u, T = (t.empty(nc, dtype=t.float64, device=self.device) for _ in range(3))
+        _check(lib().hhlb_moments(self.h, ctypes.c_void_p(n.data_ptr()),
+                                  ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(T.data_ptr())))
+        return n, u, T
+
+    def diagnostics(self):
+        t = self.torch
+        nch = len(self.channels)
+        nw = t.empty(2 * nch, dtype=t.float64, device=self.device)
+        mass = t.empty(nch, dtype=t.float64, device=self.device)
+        bad = t.empty(1, dtype=t.int32, device=self.device)
+        _check(lib().hhlb_diagnostics(self.h, ctypes.c_void_p(nw.data_ptr()),
+                                      ctypes.c_void_p(mass.data_ptr()),
+                                      ctypes.c_void_p(bad.data_ptr())))
+        return nw.view(nch, 2), mass, bad
+
+    def launch_info(self):
+        a, b = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().hhlb_launch_info(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    # -- helpers ----------------------------------------------------------
+    def channel_view(self, flat, c: int):
+        """(V, Nx) view of channel c inside a flat state array."""
+        ch = self.channels[c]
+        return flat[self.offsets[c]:self.offsets[c + 1]].view(ch.V, ch.Nx)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hhlb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

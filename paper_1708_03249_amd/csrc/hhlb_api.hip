@@ -1,0 +1,616 @@
+// C ABI of the half-range lattice Boltzmann step library (declared in
+// include/hhlb.h): argument checking, host tables, workspace layout, and the
+// launch sequence of the three RK-3 stages.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/hhlb.h"
+#include "step_kernels.hpp"
+#include "tables.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+hhlb_status fail(hhlb_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) return fail(HHLB_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+using Launcher = void (*)(const hhlb::StageArgs &, hipStream_t);
+
+template <int QUAD, int Q, int NF, int ADV>
+void launch_stage(const hhlb::StageArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((hhlb::stage_kernel<QUAD, Q, NF, ADV>), dim3(a.nwin), dim3(64), 0, s, a);
+}
+
+template <int QUAD, int Q>
+void add_variants(std::map<std::tuple<int, int, int, int>, Launcher> &m) {
+  m[{QUAD, Q, 1, 0}] = launch_stage<QUAD, Q, 1, 0>;
+  m[{QUAD, Q, 1, 1}] = launch_stage<QUAD, Q, 1, 1>;
+  m[{QUAD, Q, 2, 0}] = launch_stage<QUAD, Q, 2, 0>;
+  m[{QUAD, Q, 2, 1}] = launch_stage<QUAD, Q, 2, 1>;
+}
+
+const std::map<std::tuple<int, int, int, int>, Launcher> &launchers() {
+  static std::map<std::tuple<int, int, int, int>, Launcher> m = [] {
+    std::map<std::tuple<int, int, int, int>, Launcher> t;
+    add_variants<0, 1>(t);
+    add_variants<0, 2>(t);
+    add_variants<0, 3>(t);
+    add_variants<0, 4>(t);
+    add_variants<0, 6>(t);
+    add_variants<0, 8>(t);
+    add_variants<0, 12>(t);
+    add_variants<0, 16>(t);
+    add_variants<1, 2>(t);
+    add_variants<1, 4>(t);
+    add_variants<1, 8>(t);
+    add_variants<1, 16>(t);
+    return t;
+  }();
+  return m;
+}
+
+// ---- auxiliary kernels ---------------------------------------------------
+
+__global__ void moments_kernel(const hhlb::DevTables *tbs, const int32_t *ch_class,
+                               const hhlb::DevChannel *chans, const int32_t *ch_V, int n_ch,
+                               const double *f, const double *c, int has_chi, double *n_out,
+                               double *u_out, double *T_out) {
+  const int ch = blockIdx.y;
+  if (ch >= n_ch) return;
+  const hhlb::DevChannel C = chans[ch];
+  const hhlb::DevTables *tb = tbs + ch_class[ch];
+  const int V = ch_V[ch];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < C.Nx; i += gridDim.x * blockDim.x) {
+    double n = 0, mom = 0;
+    for (int k = 0; k < V; ++k) {
+      double y = f[C.off + (int64_t)k * C.Nx + i];
+      n += y;
+      mom += tb->p[k] * y;
+    }
+    double u = mom / n, e2 = 0, ech = 0;
+    for (int k = 0; k < V; ++k) {
+      double dp = tb->p[k] - u;
+      e2 += dp * dp * f[C.off + (int64_t)k * C.Nx + i];
+      if (has_chi && C.half_Dt != 0.0) ech += c[C.off + (int64_t)k * C.Nx + i];
+    }
+    n_out[C.cell_off + i] = n;
+    u_out[C.cell_off + i] = u;
+    T_out[C.cell_off + i] = (e2 + 2 * ech) * C.inv_1pDt / n;
+  }
+}
+
+__global__ void mass_kernel(const hhlb::DevChannel *chans, const int32_t *ch_V, int n_ch,
+                            const double *f, const double *c, int has_chi, const double *dx,
+                            double *mass, int32_t *nonfinite) {
+  const int ch = blockIdx.x;
+  if (ch >= n_ch) return;
+  const hhlb::DevChannel C = chans[ch];
+  const int V = ch_V[ch];
+  __shared__ double part[256];
+  double acc = 0;
+  int bad = 0;
+  for (int i = threadIdx.x; i < C.Nx; i += blockDim.x) {
+    double n = 0;
+    for (int k = 0; k < V; ++k) {
+      double y = f[C.off + (int64_t)k * C.Nx + i];
+      n += y;
+      if (!isfinite(y)) ++bad;
+      if (has_chi && C.half_Dt != 0.0 && !isfinite(c[C.off + (int64_t)k * C.Nx + i])) ++bad;
+    }
+    acc += dx[C.cell_off + i] * n;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && mass) mass[ch] = part[0];
+  if (bad && nonfinite) atomicAdd(nonfinite, bad);
+}
+
+__global__ void fill_kernel(const hhlb::DevChannel *chans, const int32_t *ch_V, int n_ch,
+                            const double *feq, const int32_t *feq_off, double T0, double *f,
+                            double *c) {
+  const int ch = blockIdx.y;
+  if (ch >= n_ch) return;
+  const hhlb::DevChannel C = chans[ch];
+  const int V = ch_V[ch];
+  const int64_t total = (int64_t)V * C.Nx;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(j / C.Nx);
+    const double y = feq[feq_off[ch] + k];
+    f[C.off + j] = y;
+    if (c) c[C.off + j] = C.half_Dt * T0 * y;
+  }
+}
+
+__global__ void zero_kernel(int32_t *p) { *p = 0; }
+
+}  // namespace
+
+// ---- solver ---------------------------------------------------------------
+
+struct ModelClass {
+  int quad, Q, N, adv, Dt;
+  double p0;
+  hhlb::Rule rule;
+  hhlb::DevTables dev;
+  Launcher launch = nullptr;
+  std::vector<hhlb::DevWindow> windows;
+  size_t win_off = 0;  // byte offset in workspace
+};
+
+struct hhlb_solver {
+  std::vector<hhlb_channel> ch;
+  std::vector<int> ch_class;
+  std::vector<ModelClass> classes;
+  std::vector<hhlb::DevChannel> dch;
+  std::vector<int64_t> off;     // state offsets (doubles), n_ch+1
+  std::vector<int32_t> cell_off;
+  std::vector<double> dx, inv_dx, gw, dts;
+  std::vector<int32_t> Vs;
+  int64_t total_state = 0, total_cells = 0;
+  bool has_chi = false;
+  hipStream_t stream = nullptr;
+  // workspace layout (byte offsets)
+  size_t o_tables = 0, o_chans = 0, o_chclass = 0, o_V = 0, o_dx = 0, o_invdx = 0, o_gw = 0,
+         o_nwall = 0, o_feq = 0, o_feqoff = 0, o_state = 0, bytes = 0;
+  char *ws = nullptr;
+  double *fA = nullptr, *fB = nullptr, *fC = nullptr, *cA = nullptr, *cB = nullptr, *cC = nullptr;
+};
+
+namespace {
+
+hhlb_status check_channel(const hhlb_channel &c, int idx) {
+  auto bad = [&](const char *what) {
+    return fail(HHLB_E_ARG, "channel " + std::to_string(idx) + ": " + what);
+  };
+  if (c.quad != HHLB_HALF_HERMITE && c.quad != HHLB_FULL_HERMITE) return bad("unknown quadrature");
+  if (c.Q < 1) return bad("Q must be >= 1");
+  if (c.quad == HHLB_FULL_HERMITE && (c.Q % 2)) return bad("full-range Q must be even");
+  int N = c.N < 0 ? std::min(20, c.Q - 1) : c.N;
+  if (N >= c.Q) return bad("N must satisfy 0 <= N < Q");
+  if (c.Nx < 8) return bad("Nx must be >= 8");
+  if (c.adv != HHLB_WENO5 && c.adv != HHLB_UPWIND3) return bad("unknown advection scheme");
+  if (c.transverse_dof != 0 && c.transverse_dof != 2) return bad("transverse_dof must be 0 or 2");
+  if (!(c.L > 0) || !std::isfinite(c.L)) return bad("L must be positive");
+  if (!(c.stretch_A >= 0 && c.stretch_A < 1)) return bad("stretch_A must be in [0,1)");
+  if (!(c.Kn > 0)) return bad("Kn must be > 0 (INFINITY for collisionless)");
+  if (!std::isfinite(c.g)) return bad("g must be finite");
+  if (!(c.T_left > 0) || !(c.T_right > 0) || !std::isfinite(c.T_left) || !std::isfinite(c.T_right))
+    return bad("wall temperatures must be positive");
+  if (!(c.p0 > 0) || !std::isfinite(c.p0)) return bad("p0 must be positive");
+  if (!(c.dt != 0) || !std::isfinite(c.dt)) return bad("dt must be non-zero and finite");
+  return HHLB_OK;
+}
+
+// Grid of Eqs. (x_eta) and (etai): faces, widths.
+void make_grid(const hhlb_channel &c, std::vector<double> &dx) {
+  const int Nx = c.Nx;
+  dx.resize(Nx);
+  std::vector<long double> xf(Nx + 1);
+  if (c.stretch_A == 0.0) {
+    for (int j = 0; j <= Nx; ++j) xf[j] = -(long double)c.L / 2 + (long double)c.L * j / Nx;
+  } else {
+    long double A = c.stretch_A, deta = 2.0L / Nx * atanhl(A);
+    for (int j = 0; j <= Nx; ++j) xf[j] = c.L / (2 * A) * tanhl((j + 0.5L - (Nx + 1) / 2.0L) * deta);
+  }
+  for (int i = 0; i < Nx; ++i) dx[i] = (double)(xf[i + 1] - xf[i]);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hhlb_last_error(void) { return g_err.c_str(); }
+
+hhlb_status hhlb_nodes(int32_t quad, int32_t Q, double p0, double *p_out, double *w_out) {
+  if (!p_out || !w_out) return fail(HHLB_E_ARG, "null output pointer");
+  try {
+    hhlb::Rule r;
+    std::string err;
+    int st = hhlb::build_rule(quad, Q, p0, r, err);
+    if (st) return fail(st, err);
+    std::memcpy(p_out, r.p.data(), sizeof(double) * r.V);
+    std::memcpy(w_out, r.wv.data(), sizeof(double) * r.V);
+  } catch (...) {
+    return fail(HHLB_E_NOMEM, "allocation failed");
+  }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_force_matrix(int32_t quad, int32_t Q, double p0, double *K_out) {
+  if (!K_out) return fail(HHLB_E_ARG, "null output pointer");
+  try {
+    hhlb::Rule r;
+    std::string err;
+    int st = hhlb::build_rule(quad, Q, p0, r, err);
+    if (st) return fail(st, err);
+    std::memcpy(K_out, r.K.data(), sizeof(double) * r.V * r.V);
+  } catch (...) {
+    return fail(HHLB_E_NOMEM, "allocation failed");
+  }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_equilibrium(int32_t quad, int32_t Q, int32_t N, double p0, double n, double u,
+                             double T, double *feq_out) {
+  if (!feq_out) return fail(HHLB_E_ARG, "null output pointer");
+  if (N < 0 || N >= Q) return fail(HHLB_E_ARG, "N must satisfy 0 <= N < Q");
+  if (!(T > 0) || !std::isfinite(u) || !std::isfinite(n)) return fail(HHLB_E_ARG, "need T > 0, finite n, u");
+  try {
+    hhlb::Rule r;
+    std::string err;
+    int st = hhlb::build_rule(quad, Q, p0, r, err);
+    if (st) return fail(st, err);
+    hhlb::equilibrium(r, N, u, T, feq_out);
+    for (int k = 0; k < r.V; ++k) feq_out[k] *= n;
+  } catch (...) {
+    return fail(HHLB_E_NOMEM, "allocation failed");
+  }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t precision,
+                        void *hip_stream, hhlb_solver **out) {
+  if (!channels || !out || n_ch < 1) return fail(HHLB_E_ARG, "need channels, n_ch >= 1 and out");
+  if (precision != HHLB_FP64) return fail(HHLB_E_UNSUPPORTED, "only HHLB_FP64 is available");
+  for (int c = 0; c < n_ch; ++c) {
+    hhlb_status st = check_channel(channels[c], c);
+    if (st) return st;
+  }
+  std::unique_ptr<hhlb_solver> s;
+  try {
+    s.reset(new hhlb_solver());
+    s->stream = (hipStream_t)hip_stream;
+    s->ch.assign(channels, channels + n_ch);
+    std::map<std::tuple<int, int, int, int, int, double>, int> cls;
+    s->off.assign(n_ch + 1, 0);
+    s->cell_off.assign(n_ch, 0);
+    for (int c = 0; c < n_ch; ++c) {
+      const hhlb_channel &h = channels[c];
+      int N = h.N < 0 ? std::min(20, h.Q - 1) : h.N;
+      auto key = std::make_tuple(h.quad, h.Q, N, h.adv, h.transverse_dof, h.p0);
+      auto it = cls.find(key);
+      int id;
+      if (it == cls.end()) {
+        ModelClass mc;
+        mc.quad = h.quad; mc.Q = h.Q; mc.N = N; mc.adv = h.adv; mc.Dt = h.transverse_dof; mc.p0 = h.p0;
+        std::string err;
+        int st = hhlb::build_rule(h.quad, h.Q, h.p0, mc.rule, err);
+        if (st) return fail(st, "channel " + std::to_string(c) + ": " + err);
+        auto lk = launchers().find({h.quad, h.Q, h.transverse_dof > 0 ? 2 : 1, h.adv});
+        if (lk == launchers().end())
+          return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) + ": no kernel for quad=" +
+                                              std::to_string(h.quad) + " Q=" + std::to_string(h.Q));
+        mc.launch = lk->second;
+        // device tables
+        hhlb::DevTables &d = mc.dev;
+        std::memset(&d, 0, sizeof(d));
+        const hhlb::Rule &r = mc.rule;
+        for (int k = 0; k < r.V; ++k) d.p[k] = r.p[k];
+        for (int k = 0; k < r.H; ++k) { d.z[k] = (double)r.z[k]; d.w[k] = (double)r.w[k]; }
+        for (int l = 0; l < h.Q + 1 && l < (int)r.a.size(); ++l) d.a[l] = (double)r.a[l];
+        for (int l = 0; l < h.Q + 2 && l < (int)r.b.size(); ++l) {
+          d.sb[l] = (double)sqrtl(r.b[l]);
+          d.isb[l] = (double)(1.0L / sqrtl(r.b[l]));
+        }
+        if (h.quad == HHLB_HALF_HERMITE) {
+          for (int j = 0; j < r.H * r.H; ++j) d.Kin[j] = r.Kin[j];
+          for (int k = 0; k < r.H; ++k) { d.ka[k] = r.ka[k]; d.kb[k] = r.kb[k]; }
+          for (int k = 0; k < r.H; ++k)
+            for (int l = 0; l < h.Q; ++l) d.HW[k * h.Q + l] = l <= N ? r.HW[(size_t)k * h.Q + l] : 0.0;
+        } else {
+          for (int j = 0; j < r.V * r.V; ++j) d.Kin[j] = r.K[j];
+          for (int k = 0; k < r.V; ++k)
+            for (int l = 0; l < h.Q; ++l) d.HW[k * h.Q + l] = l <= N ? r.HW[(size_t)k * h.Q + l] : 0.0;
+        }
+        std::vector<long double> tau, lam;
+        hhlb::gauss_legendre01(hhlb::kNc, tau, lam);
+        const long double inv_s2pi = 1.0L / sqrtl(2 * 3.141592653589793238462643383279502884L);
+        for (int j = 0; j < hhlb::kNc; ++j) { d.tau[j] = (double)tau[j]; d.lamw[j] = (double)(lam[j] * inv_s2pi); }
+        d.inv_p0 = 1.0 / h.p0;
+        id = (int)s->classes.size();
+        s->classes.push_back(std::move(mc));
+        cls[key] = id;
+      } else {
+        id = it->second;
+      }
+      s->ch_class.push_back(id);
+      const ModelClass &mc = s->classes[id];
+      const int V = mc.rule.V;
+      s->Vs.push_back(V);
+      s->off[c + 1] = s->off[c] + (int64_t)V * h.Nx;
+      s->cell_off[c] = (int32_t)s->total_cells;
+      s->total_cells += h.Nx;
+      if (h.transverse_dof > 0) s->has_chi = true;
+    }
+    s->total_state = s->off[n_ch];
+    if (s->total_cells > INT32_MAX / 2) return fail(HHLB_E_UNSUPPORTED, "too many cells");
+    // per channel: grid, dt, wall equilibria, denominators, windows
+    for (int c = 0; c < n_ch; ++c) {
+      const hhlb_channel &h = channels[c];
+      ModelClass &mc = s->classes[s->ch_class[c]];
+      const hhlb::Rule &r = mc.rule;
+      std::vector<double> dx;
+      make_grid(h, dx);
+      double dxmin = dx[0];
+      for (double d : dx) dxmin = std::min(dxmin, d);
+      for (double d : dx) { s->dx.push_back(d); s->inv_dx.push_back(1.0 / d); }
+      double vmax = 0;
+      for (double p : r.p) vmax = std::max(vmax, std::fabs(p));
+      double dt = h.dt;
+      if (dt < 0) {
+        dt = -dt * dxmin / vmax;
+        if (std::isfinite(h.Kn)) dt = std::min(dt, 0.5 * h.Kn);
+      }
+      s->dts.push_back(dt);
+      std::vector<double> gL(r.V), gR(r.V);
+      hhlb::equilibrium(r, mc.N, 0.0L, (long double)h.T_left, gL.data());
+      hhlb::equilibrium(r, mc.N, 0.0L, (long double)h.T_right, gR.data());
+      long double DL = 0, DR = 0;
+      for (int k = 0; k < r.V; ++k) {
+        if (k < r.H) DL += (long double)r.p[k] * gL[k];
+        else DR += (long double)r.p[k] * gR[k];
+      }
+      hhlb::DevChannel d;
+      std::memset(&d, 0, sizeof(d));
+      d.off = s->off[c];
+      d.Nx = h.Nx;
+      d.cell_off = s->cell_off[c];
+      d.gw_off = (int32_t)s->gw.size();
+      for (double v : gL) s->gw.push_back(v);
+      for (double v : gR) s->gw.push_back(v);
+      d.g = h.g;
+      d.inv_Kn = std::isfinite(h.Kn) ? 1.0 / h.Kn : 0.0;
+      d.dt = dt;
+      d.TL = h.T_left;
+      d.TR = h.T_right;
+      d.inv_DL = (double)(1.0L / DL);
+      d.inv_DR = (double)(1.0L / DR);
+      d.half_Dt = 0.5 * h.transverse_dof;
+      d.inv_1pDt = 1.0 / (1.0 + h.transverse_dof);
+      s->dch.push_back(d);
+      for (int i0 = 0; i0 < h.Nx; i0 += hhlb::kWin) mc.windows.push_back({c, i0});
+    }
+    // workspace layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r0 = o; o = align256(o + bytes); return r0; };
+    s->o_tables = take(sizeof(hhlb::DevTables) * s->classes.size());
+    s->o_chans = take(sizeof(hhlb::DevChannel) * n_ch);
+    s->o_chclass = take(sizeof(int32_t) * n_ch);
+    s->o_V = take(sizeof(int32_t) * n_ch);
+    for (auto &mc : s->classes) mc.win_off = take(sizeof(hhlb::DevWindow) * mc.windows.size());
+    s->o_dx = take(sizeof(double) * s->total_cells);
+    s->o_invdx = take(sizeof(double) * s->total_cells);
+    s->o_gw = take(sizeof(double) * s->gw.size());
+    s->o_nwall = take(sizeof(double) * 2 * n_ch);
+    int64_t feq_total = 0;
+    for (int c = 0; c < n_ch; ++c) feq_total += s->Vs[c];
+    s->o_feq = take(sizeof(double) * feq_total);
+    s->o_feqoff = take(sizeof(int32_t) * n_ch);
+    s->o_state = o;
+    const int ncopies = s->has_chi ? 6 : 3;
+    for (int j = 0; j < ncopies; ++j) take(sizeof(double) * s->total_state);
+    s->bytes = o;
+  } catch (...) {
+    return fail(HHLB_E_NOMEM, "host allocation failed");
+  }
+  *out = s.release();
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_workspace_bytes(const hhlb_solver *s, size_t *bytes) {
+  if (!s || !bytes) return fail(HHLB_E_ARG, "null argument");
+  *bytes = s->bytes;
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr) {
+  if (!s || !dev_ptr) return fail(HHLB_E_ARG, "null argument");
+  if (((uintptr_t)dev_ptr) & 255) return fail(HHLB_E_ARG, "workspace must be 256-byte aligned");
+  char *ws = (char *)dev_ptr;
+  const int n_ch = (int)s->ch.size();
+  std::vector<hhlb::DevTables> tabs;
+  for (auto &mc : s->classes) tabs.push_back(mc.dev);
+  std::vector<int32_t> feq_off(n_ch);
+  int64_t acc = 0;
+  for (int c = 0; c < n_ch; ++c) { feq_off[c] = (int32_t)acc; acc += s->Vs[c]; }
+  HIP_TRY(hipMemcpyAsync(ws + s->o_tables, tabs.data(), sizeof(hhlb::DevTables) * tabs.size(),
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(ws + s->o_chans, s->dch.data(), sizeof(hhlb::DevChannel) * n_ch,
+                         hipMemcpyHostToDevice, s->stream));
+  std::vector<int32_t> chclass(s->ch_class.begin(), s->ch_class.end());
+  HIP_TRY(hipMemcpyAsync(ws + s->o_chclass, chclass.data(), sizeof(int32_t) * n_ch,
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(ws + s->o_V, s->Vs.data(), sizeof(int32_t) * n_ch, hipMemcpyHostToDevice,
+                         s->stream));
+  for (auto &mc : s->classes)
+    HIP_TRY(hipMemcpyAsync(ws + mc.win_off, mc.windows.data(), sizeof(hhlb::DevWindow) * mc.windows.size(),
+                           hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(ws + s->o_dx, s->dx.data(), sizeof(double) * s->total_cells,
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(ws + s->o_invdx, s->inv_dx.data(), sizeof(double) * s->total_cells,
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(ws + s->o_gw, s->gw.data(), sizeof(double) * s->gw.size(),
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(ws + s->o_feqoff, feq_off.data(), sizeof(int32_t) * n_ch,
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemsetAsync(ws + s->o_nwall, 0, sizeof(double) * 2 * n_ch, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->ws = ws;
+  double *st = (double *)(ws + s->o_state);
+  const size_t stride = align256(sizeof(double) * s->total_state) / sizeof(double);
+  s->fA = st; s->fB = st + stride; s->fC = st + 2 * stride;
+  if (s->has_chi) { s->cA = st + 3 * stride; s->cB = st + 4 * stride; s->cC = st + 5 * stride; }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_state_offsets(const hhlb_solver *s, int64_t *off) {
+  if (!s || !off) return fail(HHLB_E_ARG, "null argument");
+  std::memcpy(off, s->off.data(), sizeof(int64_t) * s->off.size());
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_time_steps(const hhlb_solver *s, double *dt_out) {
+  if (!s || !dt_out) return fail(HHLB_E_ARG, "null argument");
+  std::memcpy(dt_out, s->dts.data(), sizeof(double) * s->dts.size());
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_set_state(hhlb_solver *s, const double *f_dev, const double *chi_dev) {
+  if (!s || !f_dev) return fail(HHLB_E_ARG, "null argument");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  if (s->has_chi && !chi_dev) return fail(HHLB_E_ARG, "chi is required when a channel has Dt > 0");
+  HIP_TRY(hipMemcpyAsync(s->fA, f_dev, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
+  if (s->has_chi)
+    HIP_TRY(hipMemcpyAsync(s->cA, chi_dev, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_get_state(const hhlb_solver *s, double *f_dev, double *chi_dev) {
+  if (!s || !f_dev) return fail(HHLB_E_ARG, "null argument");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  HIP_TRY(hipMemcpyAsync(f_dev, s->fA, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
+  if (chi_dev) {
+    if (s->has_chi)
+      HIP_TRY(hipMemcpyAsync(chi_dev, s->cA, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
+    else
+      HIP_TRY(hipMemsetAsync(chi_dev, 0, sizeof(double) * s->total_state, s->stream));
+  }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_init_equilibrium(hhlb_solver *s, double n0, double u0, double T0) {
+  if (!s) return fail(HHLB_E_ARG, "null solver");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  if (!(T0 > 0) || !std::isfinite(n0) || !std::isfinite(u0)) return fail(HHLB_E_ARG, "need T0 > 0, finite n0, u0");
+  const int n_ch = (int)s->ch.size();
+  std::vector<double> feq;
+  for (int c = 0; c < n_ch; ++c) {
+    const ModelClass &mc = s->classes[s->ch_class[c]];
+    std::vector<double> g(mc.rule.V);
+    hhlb::equilibrium(mc.rule, mc.N, u0, T0, g.data());
+    for (double v : g) feq.push_back(n0 * v);
+  }
+  HIP_TRY(hipMemcpyAsync(s->ws + s->o_feq, feq.data(), sizeof(double) * feq.size(), hipMemcpyHostToDevice,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  int64_t maxlen = 0;
+  for (int c = 0; c < n_ch; ++c) maxlen = std::max<int64_t>(maxlen, s->off[c + 1] - s->off[c]);
+  dim3 grid((unsigned)std::min<int64_t>((maxlen + 255) / 256, 4096), n_ch);
+  hipLaunchKernelGGL(fill_kernel, grid, dim3(256), 0, s->stream,
+                     (const hhlb::DevChannel *)(s->ws + s->o_chans), (const int32_t *)(s->ws + s->o_V), n_ch,
+                     (const double *)(s->ws + s->o_feq), (const int32_t *)(s->ws + s->o_feqoff), T0, s->fA,
+                     s->has_chi ? s->cA : nullptr);
+  HIP_TRY(hipGetLastError());
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
+  if (!s) return fail(HHLB_E_ARG, "null solver");
+  if (n_steps < 0) return fail(HHLB_E_ARG, "n_steps must be >= 0");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  const double ab[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double bs[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int64_t step = 0; step < n_steps; ++step) {
+    for (int stage = 0; stage < 3; ++stage) {
+      const double *inf = stage == 0 ? s->fA : (stage == 1 ? s->fB : s->fC);
+      const double *inc = stage == 0 ? s->cA : (stage == 1 ? s->cB : s->cC);
+      double *outf = stage == 0 ? s->fB : (stage == 1 ? s->fC : s->fA);
+      double *outc = stage == 0 ? s->cB : (stage == 1 ? s->cC : s->cA);
+      for (size_t ci = 0; ci < s->classes.size(); ++ci) {
+        ModelClass &mc = s->classes[ci];
+        hhlb::StageArgs a;
+        a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables) + ci;
+        a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
+        a.wins = (const hhlb::DevWindow *)(s->ws + mc.win_off);
+        a.nwin = (int32_t)mc.windows.size();
+        a.stage = stage;
+        a.inv_dx = (const double *)(s->ws + s->o_invdx);
+        a.gw = (const double *)(s->ws + s->o_gw);
+        a.in_f = inf; a.in_c = inc;
+        a.base_f = s->fA; a.base_c = s->cA;
+        a.out_f = outf; a.out_c = outc;
+        a.a_base = ab[stage];
+        a.b_stage = bs[stage];
+        a.nwall = (double *)(s->ws + s->o_nwall);
+        mc.launch(a, s->stream);
+      }
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_moments(const hhlb_solver *s, double *n_dev, double *u_dev, double *T_dev) {
+  if (!s || !n_dev || !u_dev || !T_dev) return fail(HHLB_E_ARG, "null argument");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  const int n_ch = (int)s->ch.size();
+  int maxNx = 0;
+  for (auto &c : s->ch) maxNx = std::max(maxNx, c.Nx);
+  dim3 grid((maxNx + 255) / 256, n_ch);
+  hipLaunchKernelGGL(moments_kernel, grid, dim3(256), 0, s->stream,
+                     (const hhlb::DevTables *)(s->ws + s->o_tables), (const int32_t *)(s->ws + s->o_chclass),
+                     (const hhlb::DevChannel *)(s->ws + s->o_chans), (const int32_t *)(s->ws + s->o_V), n_ch,
+                     s->fA, s->cA, s->has_chi ? 1 : 0, n_dev, u_dev, T_dev);
+  HIP_TRY(hipGetLastError());
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_diagnostics(const hhlb_solver *s, double *n_wall_dev, double *mass_dev,
+                             int32_t *nonfinite_dev) {
+  if (!s) return fail(HHLB_E_ARG, "null solver");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  const int n_ch = (int)s->ch.size();
+  if (n_wall_dev)
+    HIP_TRY(hipMemcpyAsync(n_wall_dev, s->ws + s->o_nwall, sizeof(double) * 2 * n_ch, hipMemcpyDeviceToDevice,
+                           s->stream));
+  if (mass_dev || nonfinite_dev) {
+    if (nonfinite_dev) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, s->stream, nonfinite_dev);
+    hipLaunchKernelGGL(mass_kernel, dim3(n_ch), dim3(256), 0, s->stream,
+                       (const hhlb::DevChannel *)(s->ws + s->o_chans), (const int32_t *)(s->ws + s->o_V), n_ch,
+                       s->fA, s->cA, s->has_chi ? 1 : 0, (const double *)(s->ws + s->o_dx), mass_dev,
+                       nonfinite_dev);
+    HIP_TRY(hipGetLastError());
+  }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_launch_info(const hhlb_solver *s, int32_t *launches_per_stage, int64_t *windows_total) {
+  if (!s) return fail(HHLB_E_ARG, "null solver");
+  if (launches_per_stage) *launches_per_stage = (int32_t)s->classes.size();
+  if (windows_total) {
+    int64_t t = 0;
+    for (auto &mc : s->classes) t += (int64_t)mc.windows.size();
+    *windows_total = t;
+  }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_destroy(hhlb_solver *s) {
+  delete s;
+  return HHLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,341 @@
+// Host table builder for the half-range (Sec. IV.B) and full-range
+// (Sec. IV.A) Gauss-Hermite lattice Boltzmann models.
+//
+// Half-range Hermite polynomials are generated from their three-term
+// recurrence (Appendix B), whose coefficients come from a discretised
+// Stieltjes procedure on a fine composite Gauss-Legendre grid of [0, 40];
+// nodes are the eigenvalues of the Jacobi matrix (Eq. hh_A_matrix; found by
+// Sturm-sequence bisection) and weights the Christoffel numbers
+// 1 / sum_{l<Q} h_l(z_k)^2.  Everything is evaluated in long double through
+// the recurrence (never through monomial coefficients) and rounded once.
+#include "tables.hpp"
+
+#include <cmath>
+
+#include "../../include/hhlb.h"
+
+namespace hhlb {
+
+namespace {
+
+using ld = long double;
+const ld kPi = 3.141592653589793238462643383279502884L;
+
+// Legendre P_n and derivative at x by recurrence.
+void legendre(int n, ld x, ld &p, ld &dp) {
+  ld p0 = 1, p1 = x;
+  if (n == 0) { p = 1; dp = 0; return; }
+  for (int k = 2; k <= n; ++k) {
+    ld p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+  dp = n * (x * p1 - p0) / (x * x - 1);
+}
+
+// Orthonormal polynomial values h_0..h_n at x from the recurrence.
+void ortho_values(const Rule &r, int n, ld x, ld *h) {
+  h[0] = 1 / sqrtl(r.b[0]);
+  if (n >= 1) h[1] = (x - r.a[0]) * h[0] / sqrtl(r.b[1]);
+  for (int l = 1; l < n; ++l) h[l + 1] = ((x - r.a[l]) * h[l] - sqrtl(r.b[l]) * h[l - 1]) / sqrtl(r.b[l + 1]);
+}
+
+// Number of eigenvalues of the n x n Jacobi matrix below x (Sturm count).
+int sturm_count(const Rule &r, int n, ld x) {
+  int cnt = 0;
+  ld d = 1;
+  for (int i = 0; i < n; ++i) {
+    ld off2 = (i == 0) ? 0 : r.b[i];
+    ld dn = (r.a[i] - x) - (i == 0 ? 0 : off2 / d);
+    if (dn == 0) dn = -1e-4000L;
+    if (dn < 0) ++cnt;
+    d = dn;
+  }
+  return cnt;
+}
+
+// Discretised Stieltjes procedure for omega(z) = exp(-z^2/2)/sqrt(2 pi) on
+// [0, inf): returns a[0..n-1], b[0..n] of the monic recurrence
+// pi_{l+1} = (z - a_l) pi_l - b_l pi_{l-1}, b_0 = int omega.
+void stieltjes_half(int n, std::vector<ld> &a, std::vector<ld> &b) {
+  const int panels = 80, per = 48;
+  const ld width = 0.5L;
+  std::vector<ld> gx(per), gw(per);
+  {
+    std::vector<ld> tau, lam;
+    gauss_legendre01(per, tau, lam);
+    for (int i = 0; i < per; ++i) { gx[i] = tau[i]; gw[i] = lam[i]; }
+  }
+  const int M = panels * per;
+  std::vector<ld> x(M), wt(M), pk(M), pkm1(M, 0), tmp(M);
+  for (int pnl = 0; pnl < panels; ++pnl)
+    for (int i = 0; i < per; ++i) {
+      ld zz = (pnl + gx[i]) * width;
+      x[pnl * per + i] = zz;
+      wt[pnl * per + i] = gw[i] * width * expl(-zz * zz / 2) / sqrtl(2 * kPi);
+    }
+  a.assign(n, 0);
+  b.assign(n + 1, 0);
+  // normalised (Lanczos) form: q_l = pi_l / ||pi_l||
+  ld nrm = 0;
+  for (int j = 0; j < M; ++j) nrm += wt[j];
+  b[0] = nrm;
+  for (int j = 0; j < M; ++j) pk[j] = 1 / sqrtl(nrm);
+  for (int l = 0; l < n; ++l) {
+    ld al = 0;
+    for (int j = 0; j < M; ++j) al += wt[j] * x[j] * pk[j] * pk[j];
+    a[l] = al;
+    ld sb = (l == 0) ? 0 : sqrtl(b[l]);
+    for (int j = 0; j < M; ++j) tmp[j] = (x[j] - al) * pk[j] - sb * pkm1[j];
+    ld nn = 0;
+    for (int j = 0; j < M; ++j) nn += wt[j] * tmp[j] * tmp[j];
+    b[l + 1] = nn;
+    ld inv = 1 / sqrtl(nn);
+    for (int j = 0; j < M; ++j) { pkm1[j] = pk[j]; pk[j] = tmp[j] * inv; }
+  }
+}
+
+// Eigenvalues of the leading n x n Jacobi matrix by bisection.
+void jacobi_eigenvalues(const Rule &r, int n, ld lo, ld hi, std::vector<ld> &ev) {
+  ev.resize(n);
+  for (int k = 0; k < n; ++k) {
+    ld a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+      ld m = (a + b) / 2;
+      if (m <= a || m >= b) break;
+      if (sturm_count(r, n, m) > k) b = m; else a = m;
+    }
+    ev[k] = (a + b) / 2;
+  }
+}
+
+}  // namespace
+
+void gauss_legendre01(int n, std::vector<ld> &tau, std::vector<ld> &lam) {
+  tau.resize(n);
+  lam.resize(n);
+  for (int i = 0; i < n; ++i) {
+    ld x = cosl(kPi * (i + 0.75L) / (n + 0.5L));
+    for (int it = 0; it < 100; ++it) {
+      ld p, dp;
+      legendre(n, x, p, dp);
+      ld dx = p / dp;
+      x -= dx;
+      if (fabsl(dx) < 1e-22L) break;
+    }
+    ld p, dp;
+    legendre(n, x, p, dp);
+    // map [-1,1] -> [0,1]: weights 2/((1-x^2) P_n'(x)^2) halve
+    tau[i] = (x + 1) / 2;
+    lam[i] = 1 / ((1 - x * x) * dp * dp);
+  }
+  // sort ascending
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j)
+      if (tau[j] < tau[i]) { std::swap(tau[i], tau[j]); std::swap(lam[i], lam[j]); }
+}
+
+int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
+  if (Q < 1 || Q > kQmaxTables) { err = "Q out of range"; return HHLB_E_ARG; }
+  if (!(p0 > 0) || !std::isfinite(p0)) { err = "p0 must be positive"; return HHLB_E_ARG; }
+  if (quad == kFull && (Q % 2)) { err = "full-range Q must be even (no node at p = 0)"; return HHLB_E_ARG; }
+  if (quad != kHalf && quad != kFull) { err = "unknown quadrature"; return HHLB_E_ARG; }
+  r = Rule();
+  r.quad = quad; r.Q = Q; r.p0 = p0;
+  r.V = quad == kHalf ? 2 * Q : Q;
+  r.H = r.V / 2;
+  const int V = r.V, H = r.H;
+  const ld lp0 = p0;
+  if (quad == kHalf) {
+    stieltjes_half(Q + 2, r.a, r.b);
+  } else {
+    // probabilists' Hermite: monic recurrence with a_l = 0, b_l = l, b_0 = 1
+    r.a.assign(Q + 2, 0);
+    r.b.assign(Q + 3, 0);
+    r.b[0] = 1;
+    for (int l = 1; l <= Q + 2; ++l) r.b[l] = l;
+  }
+  // nodes and Christoffel weights
+  std::vector<ld> ev;
+  ld hi = 8 + 4 * sqrtl((ld)Q);
+  jacobi_eigenvalues(r, Q, quad == kHalf ? 0 : -hi, hi, ev);
+  std::vector<ld> h(Q + 2);
+  std::vector<ld> zall(Q), wall(Q);
+  for (int k = 0; k < Q; ++k) {
+    ortho_values(r, Q - 1, ev[k], h.data());
+    ld s = 0;
+    for (int l = 0; l < Q; ++l) s += h[l] * h[l];
+    zall[k] = ev[k];
+    wall[k] = 1 / s;
+  }
+  r.z.resize(H);
+  r.w.resize(H);
+  if (quad == kHalf) {
+    for (int k = 0; k < H; ++k) { r.z[k] = zall[k]; r.w[k] = wall[k]; }
+  } else {
+    for (int k = 0; k < H; ++k) { r.z[k] = zall[H + k]; r.w[k] = wall[H + k]; }
+  }
+  // self-check: exactness for degree <= 2Q-1 against the weight's moments
+  {
+    std::vector<ld> mu(2 * Q + 1);
+    if (quad == kHalf) {
+      mu[0] = 0.5L;
+      mu[1] = 1 / sqrtl(2 * kPi);
+    } else {
+      mu[0] = 1;
+      mu[1] = 0;
+    }
+    for (int s = 2; s <= 2 * Q; ++s) mu[s] = (s - 1) * mu[s - 2];
+    for (int s = 0; s < 2 * Q; ++s) {
+      ld acc = 0;
+      for (int k = 0; k < Q; ++k) acc += wall[k] * powl(zall[k], s);
+      ld ref = mu[s];
+      ld scale = 0;
+      for (int k = 0; k < Q; ++k) scale += wall[k] * powl(fabsl(zall[k]), s);
+      if (fabsl(acc - ref) > 1e-15L * scale) {
+        err = "quadrature self-check failed";
+        return HHLB_E_NUMERIC;
+      }
+    }
+  }
+  r.p.resize(V);
+  r.wv.resize(V);
+  for (int k = 0; k < V; ++k) {
+    int kk = k % H;
+    r.p[k] = (double)((k < H ? 1 : -1) * lp0 * r.z[kk]);
+    r.wv[k] = (double)r.w[kk];
+  }
+  r.K.assign((size_t)V * V, 0.0);
+  r.HW.assign((size_t)(quad == kHalf ? H : V) * Q, 0.0);
+  if (quad == kHalf) {
+    // Eq. (hh_Kk_hh) through the recurrence: h_{l,0} = h_l(0),
+    // h_{l,l}/h_{l+1,l+1} = 1/a_l = sqrt(b_{l+1}); Phi^Q_0 of Eq. (Phi_def_hh).
+    std::vector<ld> h0(Q + 1);
+    ortho_values(r, Q, 0.0L, h0.data());
+    std::vector<std::vector<ld>> hz(H, std::vector<ld>(Q + 1));
+    for (int k = 0; k < H; ++k) ortho_values(r, Q, r.z[k], hz[k].data());
+    const ld s2pi = sqrtl(2 * kPi);
+    std::vector<ld> Phi0(H);
+    for (int k = 0; k < H; ++k) {
+      ld acc = 0;
+      for (int s = 0; s < Q; ++s) acc += h0[s] * hz[k][s];
+      Phi0[k] = acc;
+    }
+    std::vector<ld> inner((size_t)H * H);
+    for (int k = 0; k < H; ++k)
+      for (int kp = 0; kp < H; ++kp) {
+        ld acc = 0;
+        for (int l = 0; l <= Q - 2; ++l) {
+          ld tail = 0;
+          for (int s = l + 1; s <= Q - 1; ++s) tail += h0[s] * hz[k][s];
+          acc += hz[kp][l] * (h0[l] / s2pi * tail - sqrtl(r.b[l + 1]) * hz[k][l + 1]);
+        }
+        inner[(size_t)k * H + kp] = acc;
+      }
+    r.Kin.assign((size_t)H * H, 0.0);
+    r.ka.assign(H, 0.0);
+    r.kb.assign(H, 0.0);
+    for (int k = 0; k < H; ++k) {
+      r.ka[k] = (double)(-(r.w[k] / lp0) * Phi0[k] / (2 * s2pi));
+      r.kb[k] = (double)Phi0[k];
+      for (int kp = 0; kp < H; ++kp) r.Kin[(size_t)k * H + kp] = (double)(r.w[k] / lp0 * inner[(size_t)k * H + kp]);
+    }
+    for (int k = 0; k < V; ++k)
+      for (int kp = 0; kp < V; ++kp) {
+        int kk = k % H, kq = kp % H;
+        ld sk = k < H ? 1 : -1, skp = kp < H ? 1 : -1;
+        ld within = (k < H) == (kp < H) ? sk * r.w[kk] / lp0 * inner[(size_t)kk * H + kq] : 0;
+        ld cross = -(sk * r.w[kk] / lp0) * Phi0[kk] * Phi0[kq] / (2 * s2pi);
+        r.K[(size_t)k * V + kp] = (double)(within + cross);
+      }
+    for (int k = 0; k < H; ++k)
+      for (int l = 0; l < Q; ++l) r.HW[(size_t)k * Q + l] = (double)(r.w[k] * hz[k][l]);
+  } else {
+    // Eq. (H_Kk) with He_l = sqrt(l!) h_l (orthonormal h_l):
+    // He_{l+1}(z_k) He_l(z_k')/l! = sqrt(l+1) h_{l+1}(z_k) h_l(z_k').
+    std::vector<std::vector<ld>> hz(V, std::vector<ld>(Q + 1));
+    std::vector<ld> zz(V);
+    for (int k = 0; k < V; ++k) {
+      zz[k] = (k < H ? 1 : -1) * r.z[k % H];
+      ortho_values(r, Q, zz[k], hz[k].data());
+    }
+    for (int k = 0; k < V; ++k)
+      for (int kp = 0; kp < V; ++kp) {
+        ld acc = 0;
+        for (int l = 0; l <= Q - 2; ++l) acc += sqrtl((ld)(l + 1)) * hz[k][l + 1] * hz[kp][l];
+        r.K[(size_t)k * V + kp] = (double)(-(r.w[k % H] / lp0) * acc);
+      }
+    // He_l(z)/l! = h_l(z)/sqrt(l!)
+    for (int k = 0; k < V; ++k) {
+      ld fact = 1;
+      for (int l = 0; l < Q; ++l) {
+        if (l > 0) fact *= l;
+        r.HW[(size_t)k * Q + l] = (double)(r.w[k % H] * hz[k][l] / sqrtl(fact));
+      }
+    }
+  }
+  return HHLB_OK;
+}
+
+// Half-range equilibrium by an exact change of variables.  With
+// p = m u + sqrt(m T) y the Maxwellian becomes the standard normal density,
+// so the coefficient G^+_l = int_0^inf dp g h_l(p/p0) of Sec. IV.B.3 is
+//   int_{y0}^inf omega(y) h_l(ub + s y) dy,   ub = m u/p0, s = sqrt(mT)/p0,
+// y0 = -u sqrt(m/T): the part on [0, inf) is a polynomial of degree <= N
+// against the half-range weight, integrated exactly by the Q-point rule
+// itself; the remainder over [y0, 0] is a short Gauss-Legendre integral.
+// G^-_l follows with u -> -u.  Then g_k = w_k sum_{l<=N} G^sigma_l h_l(z_k).
+// Full range (Sec. IV.A.3): G_l = E[He_l(X)], X ~ N(ub, mT/p0^2), from
+// G_{l+1} = ub G_l + l (mT/p0^2 - 1) G_{l-1}; g_k = w_k sum G_l He_l(z_k)/l!.
+void equilibrium(const Rule &r, int N, ld u, ld T, double *g) {
+  const int Q = r.Q, H = r.H;
+  const ld m = 1, p0 = r.p0;
+  if (r.quad == kFull) {
+    ld a = m * T / (p0 * p0) - 1, bb = m * u / p0;
+    std::vector<ld> G(N + 1);
+    G[0] = 1;
+    if (N >= 1) G[1] = bb;
+    for (int l = 1; l < N; ++l) G[l + 1] = bb * G[l] + l * a * G[l - 1];
+    std::vector<ld> h(Q + 1);
+    for (int k = 0; k < r.V; ++k) {
+      ld z = (k < H ? 1 : -1) * r.z[k % H];
+      ortho_values(r, N, z, h.data());
+      ld acc = 0, fact = 1;
+      for (int l = 0; l <= N; ++l) {
+        if (l > 0) fact *= l;
+        acc += G[l] * h[l] / sqrtl(fact);
+      }
+      g[k] = (double)(r.w[k % H] * acc);
+    }
+    return;
+  }
+  std::vector<ld> tau, lam;
+  gauss_legendre01(16, tau, lam);
+  ld ub = m * u / p0, s = sqrtl(m * T) / p0, y0 = -u * sqrtl(m / T);
+  std::vector<ld> h(Q + 1), Gp(N + 1, 0), Gm(N + 1, 0);
+  for (int j = 0; j < Q; ++j) {
+    ortho_values(r, N, ub + s * r.z[j], h.data());
+    for (int l = 0; l <= N; ++l) Gp[l] += r.w[j] * h[l];
+    ortho_values(r, N, -ub + s * r.z[j], h.data());
+    for (int l = 0; l <= N; ++l) Gm[l] += r.w[j] * h[l];
+  }
+  if (y0 != 0) {
+    for (size_t i = 0; i < tau.size(); ++i) {
+      ld e = y0 * lam[i] * expl(-(y0 * tau[i]) * (y0 * tau[i]) / 2) / sqrtl(2 * kPi);
+      ortho_values(r, N, ub * (1 - tau[i]), h.data());
+      for (int l = 0; l <= N; ++l) Gp[l] -= e * h[l];
+      ortho_values(r, N, -ub * (1 - tau[i]), h.data());
+      for (int l = 0; l <= N; ++l) Gm[l] += e * h[l];
+    }
+  }
+  for (int k = 0; k < H; ++k) {
+    ortho_values(r, N, r.z[k], h.data());
+    ld ap = 0, am = 0;
+    for (int l = 0; l <= N; ++l) { ap += Gp[l] * h[l]; am += Gm[l] * h[l]; }
+    g[k] = (double)(r.w[k] * ap);
+    g[H + k] = (double)(r.w[k] * am);
+  }
+}
+
+}  // namespace hhlb

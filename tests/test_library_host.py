@@ -1,0 +1,99 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol its header
+declares, its host-built tables agree with the oracle's, and argument errors
+are reported before any side effect.  No GPU compute is called here."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1708_03249_amd as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "hhlb.h")).read()
+    names = sorted(set(re.findall(r"\b(hhlb_[a-z_]+)\s*\(", hdr)))
+    assert len(names) >= 15
+    L = H.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("quad,Q", [(H.HALF_HERMITE, q) for q in (1, 2, 3, 4, 6, 8, 12, 16)] +
+                         [(H.FULL_HERMITE, q) for q in (2, 4, 8, 16)])
+def test_host_tables_match_oracle(quad, Q):
+    p, w = H.nodes(quad, Q)
+    K = H.force_matrix(quad, Q)
+    po, wo, Ko, *_ = O.tables(quad, Q)
+    np.testing.assert_allclose(p, po, rtol=4e-15, atol=0)
+    np.testing.assert_allclose(w, wo, rtol=2e-13, atol=0)
+    np.testing.assert_allclose(K, Ko, rtol=0, atol=2e-14 * np.abs(Ko).max())
+
+
+@pytest.mark.parametrize("quad,Q", [(H.HALF_HERMITE, 4), (H.HALF_HERMITE, 8),
+                                    (H.HALF_HERMITE, 16), (H.FULL_HERMITE, 16)])
+@pytest.mark.parametrize("u,T", [(0.0, 1.0), (0.12, 1.7), (-0.3, 0.6), (0.02, 2.6)])
+def test_host_equilibrium_matches_oracle(quad, Q, u, T):
+    N = Q - 1
+    g = H.equilibrium(quad, Q, N, 1.3, u, T)
+    go = O.equilibrium(quad, Q, N, 1.3, u, T)
+    np.testing.assert_allclose(g, go, rtol=0, atol=2e-15 * np.abs(go).max())
+
+
+def test_host_equilibrium_lower_order():
+    g = H.equilibrium(H.HALF_HERMITE, 8, 4, 1.0, 0.1, 1.4)
+    go = O.equilibrium(O.HALF, 8, 4, 1.0, 0.1, 1.4)
+    np.testing.assert_allclose(g, go, rtol=0, atol=2e-15)
+
+
+def _create(channels):
+    import ctypes
+    arr = (H._CChannel * len(channels))(*[c._c() for c in channels])
+    h = ctypes.c_void_p()
+    st = H.lib().hhlb_create(arr, len(channels), H.FP64, None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("bad", [
+    dict(Q=0), dict(quad=H.FULL_HERMITE, Q=5), dict(N=4, Q=4), dict(Nx=7), dict(adv=3),
+    dict(transverse_dof=1), dict(L=0.0), dict(stretch_A=1.0), dict(stretch_A=-0.1),
+    dict(Kn=0.0), dict(Kn=-1.0), dict(T_left=0.0), dict(T_right=-1.0), dict(p0=0.0),
+    dict(dt=0.0), dict(dt=math.nan), dict(g=math.inf)])
+def test_create_rejects_bad_arguments(bad):
+    ch = H.Channel(**bad)
+    st, h = _create([H.Channel(), ch])
+    assert st == -1
+    assert "channel 1" in H.lib().hhlb_last_error().decode()
+
+
+def test_create_unsupported_shape_and_null_calls():
+    st, _ = _create([H.Channel(Q=20)])
+    assert st == -2
+    L = H.lib()
+    assert L.hhlb_step(None, 1) == -1
+    assert L.hhlb_workspace_bytes(None, None) == -1
+    st, h = _create([H.Channel()])
+    assert st == 0
+    assert L.hhlb_step(h, 1) == -6          # no workspace bound yet
+    assert L.hhlb_step(h, -1) == -1
+    import ctypes
+    nb = ctypes.c_size_t()
+    assert L.hhlb_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
+    dts = np.zeros(1)
+    assert L.hhlb_time_steps(h, H._dptr(dts)) == 0 and dts[0] == 5e-4
+    assert L.hhlb_destroy(h) == 0
+
+
+def test_cfl_time_step_resolution():
+    ch = H.Channel(Q=8, Nx=512, stretch_A=0.9, adv=H.WENO5, Kn=0.01, dt=-0.5)
+    st, h = _create([ch])
+    assert st == 0
+    dts = np.zeros(1)
+    assert H.lib().hhlb_time_steps(h, H._dptr(dts)) == 0
+    oc = O.Channel(Q=8, Nx=512, A=0.9, Kn=0.01)
+    assert dts[0] == pytest.approx(O.cfl_dt(oc, 0.5), rel=1e-12)
+    H.lib().hhlb_destroy(h)
