@@ -36,7 +36,11 @@ using Launcher = void (*)(const hhlb::StageArgs &, hipStream_t);
 
 template <int QUAD, int Q, int NF, int ADV>
 void launch_stage(const hhlb::StageArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((hhlb::stage_kernel<QUAD, Q, NF, ADV>), dim3(a.nwin), dim3(64), 0, s, a);
+  if constexpr (QUAD == 0)
+    hipLaunchKernelGGL((hhlb::stage_kernel_half<Q, NF, ADV>), dim3(a.nwin), dim3(128), 0, s, a, a.tb,
+                       a.chans, a.wins, a.inv_dx, a.gw, a.in_f, a.in_c);
+  else
+    hipLaunchKernelGGL((hhlb::stage_kernel<QUAD, Q, NF, ADV>), dim3(a.nwin), dim3(64), 0, s, a);
 }
 
 template <int QUAD, int Q>
@@ -330,6 +334,36 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
         const long double inv_s2pi = 1.0L / sqrtl(2 * 3.141592653589793238462643383279502884L);
         for (int j = 0; j < hhlb::kNc; ++j) { d.tau[j] = (double)tau[j]; d.lamw[j] = (double)(lam[j] * inv_s2pi); }
         d.inv_p0 = 1.0 / h.p0;
+        // monic recurrence and the normalisation folded into the contraction
+        {
+          long double prod = 1;
+          for (int l = 0; l < h.Q + 1 && l < (int)r.b.size(); ++l) d.mb[l] = (double)r.b[l];
+          std::vector<long double> inv_norm(h.Q);
+          for (int l = 0; l < h.Q; ++l) { prod *= r.b[l]; inv_norm[l] = 1.0L / sqrtl(prod); }
+          if (h.quad == HHLB_HALF_HERMITE)
+            for (int k = 0; k < r.H; ++k)
+              for (int l = 0; l < h.Q; ++l)
+                d.HWs[k * h.Q + l] = l <= N ? (double)((long double)r.HW[(size_t)k * h.Q + l] * inv_norm[l]) : 0.0;
+        }
+        // correction ladder (half range): point counts and the |y0| each covers
+        {
+          const int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
+          int o = 0;
+          for (int j = 0; j < hhlb::kLadder; ++j) {
+            d.lad_n[j] = counts[j];
+            d.lad_off[j] = o;
+            d.lad_y[j] = h.quad == HHLB_HALF_HERMITE ? hhlb::correction_limit(r, N, counts[j], 3e-16) : 0.0;
+            if (counts[j] > 0) {
+              std::vector<long double> t2, l2;
+              hhlb::gauss_legendre01(counts[j], t2, l2);
+              for (int q = 0; q < counts[j]; ++q) {
+                d.ltau[o + q] = (double)t2[q];
+                d.llamw[o + q] = (double)(l2[q] * inv_s2pi);
+              }
+            }
+            o += counts[j];
+          }
+        }
         id = (int)s->classes.size();
         s->classes.push_back(std::move(mc));
         cls[key] = id;

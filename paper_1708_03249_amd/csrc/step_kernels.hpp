@@ -14,7 +14,9 @@
 namespace hhlb {
 
 constexpr int kQmaxDev = 16;   // largest per-half order with a kernel
-constexpr int kNc = 8;         // Gauss-Legendre points of the equilibrium correction
+constexpr int kNc = 8;         // Gauss-Legendre points of the full-range kernel's correction
+constexpr int kLadder = 8;     // correction point counts the half-range kernel chooses from
+constexpr int kLadderPts = 64; // total points over the ladder
 constexpr int kWin = 58;       // output cells per wavefront
 constexpr int kHalo = 3;
 
@@ -30,6 +32,13 @@ struct DevTables {
   double HW[2 * kQmaxDev * kQmaxDev];     // half: H x Q; full: V x Q (zero beyond N)
   double tau[kNc], lamw[kNc];             // GL nodes in (0,1), weights * 1/sqrt(2 pi)
   double inv_p0;
+  // half-range kernel: monic recurrence q_{l+1} = (x - a_l) q_l - b_l q_{l-1}
+  double mb[kQmaxDev + 2];                // b_l
+  double HWs[kQmaxDev * kQmaxDev];        // H x Q: w_k h_l(z_k) / sqrt(b_0 .. b_l) (zero beyond N)
+  // correction ladder: count lad_n[j] is exact enough up to |y0| <= lad_y[j]
+  int lad_n[kLadder], lad_off[kLadder];
+  double lad_y[kLadder];
+  double ltau[kLadderPts], llamw[kLadderPts];
 };
 
 // Per channel.
@@ -89,6 +98,17 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// 1/x for normal, finite x > 0: the hardware estimate refined by two
+// Newton-Raphson steps (within an ulp or so; the weights it scales are
+// renormalised anyway).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // WENO-5 face value (Eqs. weno5_flux, weno5_omega, weno_sigma) for the
 // upwind-ordered stencil (a..e) = (f_{i-2}, .., f_{i+2}), with the limits of
 // Table (weno) when smoothness indicators vanish.  The weights are formed as
@@ -98,35 +118,28 @@ __device__ __forceinline__ double wave_sum(double x) {
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
   const double k13 = 13.0 / 12.0;
   double t1 = a - 2.0 * b + c, t2 = a - 4.0 * b + 3.0 * c;
-  double s1 = k13 * t1 * t1 + 0.25 * t2 * t2;
+  const double s1 = k13 * t1 * t1 + 0.25 * t2 * t2;
   t1 = b - 2.0 * c + d; t2 = b - d;
-  double s2 = k13 * t1 * t1 + 0.25 * t2 * t2;
+  const double s2 = k13 * t1 * t1 + 0.25 * t2 * t2;
   t1 = c - 2.0 * d + e; t2 = 3.0 * c - 4.0 * d + e;
-  double s3 = k13 * t1 * t1 + 0.25 * t2 * t2;
-  double F1 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
-  double F2 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
-  double F3 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
-  double smax = fmax(s1, fmax(s2, s3));
-  double q1 = 0.1, q2 = 0.6, q3 = 0.3;
-  if (smax > 0.0) {
-    int ex = 0;
-    (void)frexp(smax, &ex);
-    double r1 = ldexp(s1, -ex), r2 = ldexp(s2, -ex), r3 = ldexp(s3, -ex);
-    r1 *= r1; r2 *= r2; r3 *= r3;
-    double p1 = 0.1 * r2 * r3, p2 = 0.6 * r1 * r3, p3 = 0.3 * r1 * r2;
-    double den = p1 + p2 + p3;
-    if (den > 1e-250) {
-      double inv = 1.0 / den;
-      q1 = p1 * inv; q2 = p2 * inv; q3 = p3 * inv;
-    } else {
-      // limit: ideal weights restricted to the (relatively) vanishing sigmas
-      double tiny = 1e-125;
-      double z1 = r1 < tiny ? 0.1 : 0.0, z2 = r2 < tiny ? 0.6 : 0.0, z3 = r3 < tiny ? 0.3 : 0.0;
-      double zs = z1 + z2 + z3;
-      q1 = z1 / zs; q2 = z2 / zs; q3 = z3 / zs;
-    }
-  }
-  return q1 * F1 + q2 * F2 + q3 * F3;
+  const double s3 = k13 * t1 * t1 + 0.25 * t2 * t2;
+  const double F1 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
+  const double F2 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+  const double F3 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+  // exact power-of-two rescaling so that the largest sigma lies in [0.5, 1)
+  // (all-zero sigmas stay zero and fall through to the limit rule)
+  const int ex = __builtin_amdgcn_frexp_exp(fmax(s1, fmax(s2, s3)));
+  const double r1 = ldexp(s1, -ex), r2 = ldexp(s2, -ex), r3 = ldexp(s3, -ex);
+  const double q1s = r1 * r1, q2s = r2 * r2, q3s = r3 * r3;
+  const double p1 = 0.1 * q2s * q3s, p2 = 0.6 * q1s * q3s, p3 = 0.3 * q1s * q2s;
+  const double den = p1 + p2 + p3;
+  // limit of Table (weno): ideal weights restricted to the vanishing sigmas
+  const double tiny = 1e-125;
+  const double z1 = q1s < tiny ? 0.1 : 0.0, z2 = q2s < tiny ? 0.6 : 0.0, z3 = q3s < tiny ? 0.3 : 0.0;
+  const bool regular = den > 1e-250;
+  const double n1 = regular ? p1 : z1, n2 = regular ? p2 : z2, n3 = regular ? p3 : z3;
+  const double inv = recip(regular ? den : z1 + z2 + z3);
+  return (n1 * F1 + n2 * F2 + n3 * F3) * inv;
 }
 
 // Third-order upwind-biased face value (-f_{i-1} + 5 f_i + 2 f_{i+1})/6.
@@ -393,6 +406,260 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs A) {
         const double base = A.a_base != 0.0 ? bp[o] : 0.0;
         op[o] = A.a_base * base + A.b_stage * (yc0 + dt * L);
       }
+    }
+  }
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  lo = __builtin_amdgcn_readlane(lo, l);
+  hi = __builtin_amdgcn_readlane(hi, l);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+// Half-range kernel: the two momentum halves of a window run in the two
+// wavefronts of a 128-thread block (wave 0: p > 0, wave 1: p < 0).  Each lane
+// holds the Q nodes of its half for f and chi; the only coupling between the
+// halves -- moment sums, the rank-1 cross term of the force matrix and the
+// wall densities -- goes through 6 KB of LDS and one barrier.
+template <int Q, int NFUN, int ADV>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel_half(
+    StageArgs A, const DevTables *__restrict__ tb, const DevChannel *__restrict__ chans,
+    const DevWindow *__restrict__ wins, const double *__restrict__ inv_dx,
+    const double *__restrict__ gw, const double *__restrict__ in_f,
+    const double *__restrict__ in_c) {
+  constexpr int H = Q;
+  constexpr int NC = NFUN;
+  __shared__ double s_part[2][6][64];
+  __shared__ double s_nw[2];
+  const int hw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int w = xcd_window(blockIdx.x, A.nwin);
+  const DevWindow win = wins[w];
+  const DevChannel C = chans[win.ch];
+  const int Nx = C.Nx;
+  const int i = win.i0 - kHalo + lane;
+  const bool inside = i >= 0 && i < Nx;
+  const int kb0 = hw * H;
+  const double sg = hw ? -1.0 : 1.0;
+  const double *fin = in_f + C.off + (int64_t)kb0 * Nx;
+  const double *cin = NC > 1 ? in_c + C.off + (int64_t)kb0 * Nx : nullptr;
+
+  double yf[H], yc[NC > 1 ? H : 1];
+#pragma unroll
+  for (int j = 0; j < H; ++j) yf[j] = inside ? fin[(int64_t)j * Nx + i] : 0.0;
+  if constexpr (NC > 1) {
+#pragma unroll
+    for (int j = 0; j < H; ++j) yc[j] = inside ? cin[(int64_t)j * Nx + i] : 0.0;
+  }
+
+  // ---- closure, part 1: ghosts of the nodes flowing into a wall are
+  // extrapolated quadratically from the three nearest cells (Sec. IV.C.3) and
+  // their wall-face fluxes give the wall density (Eq. nplus_def).
+  const bool needL = win.i0 < kHalo;
+  const bool needR = win.i0 - kHalo + 63 >= Nx;
+  double nw_mine = 0.0;
+  if ((hw == 1 && needL) || (hw == 0 && needR)) {
+    const bool left = hw == 1;
+    const int l0 = left ? kHalo : Nx - 1 - (win.i0 - kHalo);   // lane of the wall cell
+    const int dl = left ? 1 : -1;
+    const int gi = left ? -i : i - Nx + 1;                      // ghost order 1..3 (else <= 0)
+    const double c0 = gi == 1 ? 3.0 : (gi == 2 ? 6.0 : 10.0);
+    const double c1 = gi == 1 ? -3.0 : (gi == 2 ? -8.0 : -15.0);
+    const double c2 = gi == 1 ? 1.0 : (gi == 2 ? 3.0 : 6.0);
+    const bool is_ghost = gi >= 1 && gi <= 3;
+    // lane j gathers node j's three wall-adjacent values; ghost lanes
+    // extrapolate every node of this half
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const double y0 = readlane_d(yf[j], l0), y1 = readlane_d(yf[j], l0 + dl),
+                   y2 = readlane_d(yf[j], l0 + 2 * dl);
+      if (lane == j) { a0 = y0; a1 = y1; a2 = y2; }
+      if (is_ghost) yf[j] = c0 * y0 + c1 * y1 + c2 * y2;
+      if constexpr (NC > 1) {
+        const double x0 = readlane_d(yc[j], l0), x1 = readlane_d(yc[j], l0 + dl),
+                     x2 = readlane_d(yc[j], l0 + 2 * dl);
+        if (is_ghost) yc[j] = c0 * x0 + c1 * x1 + c2 * x2;
+      }
+    }
+    // incoming wall-face flux of node `lane`, all nodes in parallel
+    const double g1 = 3.0 * a0 - 3.0 * a1 + a2, g2 = 6.0 * a0 - 8.0 * a1 + 3.0 * a2;
+    const double fv = face_value<ADV>(a2, a1, a0, g1, g2);
+    const double acc = wave_sum(lane < H ? tb->p[kb0 + (lane < H ? lane : 0)] * fv : 0.0);
+    nw_mine = -acc * (left ? C.inv_DL : C.inv_DR);
+  }
+
+  // ---- partial moments of this half and the rank-1 force projections ----
+  double pn = 0.0, pm = 0.0, ps = 0.0, pc = 0.0, pbf = 0.0, pbc = 0.0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double v = tb->p[kb0 + j];
+    pn += yf[j];
+    pm += v * yf[j];
+    ps += v * v * yf[j];
+    pbf += tb->kb[j] * yf[j];
+    if constexpr (NC > 1) { pc += yc[j]; pbc += tb->kb[j] * yc[j]; }
+  }
+  s_part[hw][0][lane] = pn;
+  s_part[hw][1][lane] = pm;
+  s_part[hw][2][lane] = ps;
+  s_part[hw][3][lane] = pc;
+  s_part[hw][4][lane] = pbf;
+  s_part[hw][5][lane] = pbc;
+  if (lane == 0) s_nw[hw] = nw_mine;
+  __syncthreads();
+  double n = s_part[0][0][lane] + s_part[1][0][lane];
+  double mom = s_part[0][1][lane] + s_part[1][1][lane];
+  const double s2 = s_part[0][2][lane] + s_part[1][2][lane];
+  const double ech = s_part[0][3][lane] + s_part[1][3][lane];
+  const double bf = s_part[0][4][lane] + s_part[1][4][lane];
+  const double bc = s_part[0][5][lane] + s_part[1][5][lane];
+  const double nL = s_nw[1], nR = s_nw[0];
+
+  // ---- closure, part 2: emergent ghosts n_w g^w_k in all three cells ----
+  if (hw == 0 && i < 0) {
+    const double *gwL = gw + C.gw_off;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      yf[j] = nL * gwL[j];
+      if constexpr (NC > 1) yc[j] = C.half_Dt * C.TL * yf[j];
+    }
+  }
+  if (hw == 1 && i >= Nx && i <= Nx + 2) {
+    const double *gwR = gw + C.gw_off + 2 * H + H;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      yf[j] = nR * gwR[j];
+      if constexpr (NC > 1) yc[j] = C.half_Dt * C.TR * yf[j];
+    }
+  }
+  if (A.nwall && A.stage == 2 && lane == 0) {
+    if (hw == 1 && win.i0 == 0) A.nwall[2 * win.ch] = nL;
+    if (hw == 0 && win.i0 <= Nx - 1 && Nx - 1 < win.i0 + kWin) A.nwall[2 * win.ch + 1] = nR;
+  }
+
+  // ---- moments (Eq. fmoms) ----
+  if (!inside) n = 1.0, mom = 0.0;
+  const double u = mom / n;
+  double T = (s2 - u * mom + 2.0 * ech) * C.inv_1pDt / n;
+  if (!inside) T = 1.0;
+  const double inv_tau = n * C.inv_Kn;
+
+  // ---- equilibrium coefficients of this half (monic recurrence; the
+  // normalisation is folded into HWs) ----
+  double G[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) G[l] = 0.0;
+  const bool collide = C.inv_Kn != 0.0;
+  if (collide) {
+    const double sT = sqrt(T);
+    const double ub = sg * u * tb->inv_p0, s = sT * tb->inv_p0, y0 = -u / sT;
+    auto accum = [&](double x, double wt) {
+      double qm = 1.0, q = x - tb->a[0];
+      G[0] += wt;
+      if (Q > 1) G[1] += wt * q;
+#pragma unroll
+      for (int l = 1; l + 1 < Q; ++l) {
+        const double qn = (x - tb->a[l]) * q - tb->mb[l] * qm;
+        qm = q; q = qn;
+        G[l + 1] += wt * q;
+      }
+    };
+#pragma unroll 1
+    for (int j = 0; j < Q; ++j) accum(ub + s * tb->z[j], tb->w[j]);
+    // correction over [y0, 0]: the smallest ladder entry that covers the wave
+    const double ymax = wave_max(inside ? fabs(y0) : 0.0);
+    if (ymax > 0.0) {
+      int li = kLadder - 1;
+      for (int j = 1; j < kLadder; ++j)
+        if (tb->lad_y[j] >= ymax) { li = j; break; }
+      const int nc = tb->lad_n[li], o = tb->lad_off[li];
+      for (int j = 0; j < nc; ++j) {
+        const double t = tb->ltau[o + j];
+        const double yt = y0 * t;
+        const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
+        accum(ub * (1.0 - t), -sg * e);
+      }
+    }
+  }
+
+  const bool out_lane = lane >= kHalo && lane < kHalo + kWin && inside;
+  const int ic = inside ? i : 0;   // clamped cell index: loads stay in bounds
+  const double dx_inv = inv_dx[C.cell_off + ic];
+  const int64_t obase = C.off + (int64_t)kb0 * Nx;
+  const double gforce = C.g, dt = C.dt;
+  const bool wall_face = hw == 0 ? (i == -1) : (i == Nx - 1);
+
+  // pass 1: equilibrium populations of this half
+  double geq[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) acc += tb->HWs[j * Q + l] * G[l];
+    geq[j] = acc;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // pass 2: local source -F (K y)_k - (y_k - y^eq_k)/tau for f and chi
+  double srcf[H], srcc[NC > 1 ? H : 1];
+  const double eqc = C.half_Dt * T;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    double kf = 0.0, kc = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < H; ++jj) {
+      const double kv = tb->Kin[j * H + jj];
+      kf += kv * yf[jj];
+      if constexpr (NC > 1) kc += kv * yc[jj];
+    }
+    kf = sg * (kf + tb->ka[j] * bf);
+    const double feq = n * geq[j];
+    srcf[j] = -gforce * kf - (collide ? (yf[j] - feq) * inv_tau : 0.0);
+    if constexpr (NC > 1) {
+      kc = sg * (kc + tb->ka[j] * bc);
+      srcc[j] = -gforce * kc - (collide ? (yc[j] - eqc * feq) * inv_tau : 0.0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // pass 3: advection (WENO-5 / upwind-3 face fluxes, Sec. IV.C.2) and the
+  // RK-3 combination
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double v = tb->p[kb0 + j];
+#pragma unroll
+    for (int fn = 0; fn < NC; ++fn) {
+      const double y0v = fn == 0 ? yf[j] : yc[j];
+      const double src = fn == 0 ? srcf[j] : srcc[j];
+      double F;
+      if (hw == 0) {
+        const double ym1 = dpp_shr1(y0v), ym2 = dpp_shr1(ym1);
+        const double yp1 = dpp_shl1(y0v), yp2 = dpp_shl1(yp1);
+        F = v * face_value<ADV>(ym2, ym1, y0v, yp1, yp2);
+        if (wall_face) F = v * y0v;
+      } else {
+        const double ym1 = dpp_shr1(y0v);
+        const double yp1 = dpp_shl1(y0v), yp2 = dpp_shl1(yp1), yp3 = dpp_shl1(yp2);
+        F = v * face_value<ADV>(yp3, yp2, yp1, y0v, ym1);
+        if (wall_face) F = v * yp1;
+      }
+      const double Fl = dpp_shr1(F);
+      const double L = -(F - Fl) * dx_inv + src;
+      const int64_t o = obase + (int64_t)j * Nx + ic;
+      const double *bp = fn == 0 ? A.base_f : A.base_c;
+      double *op = fn == 0 ? A.out_f : A.out_c;
+      const double base = A.a_base != 0.0 ? bp[o] : 0.0;
+      const double yn = A.a_base * base + A.b_stage * (y0v + dt * L);
+      if (out_lane) op[o] = yn;
+      // one node at a time: interleaving the unrolled WENO evaluations
+      // would exceed the register file
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }

@@ -10,6 +10,7 @@
 // the recurrence (never through monomial coefficients) and rounded once.
 #include "tables.hpp"
 
+#include <cfloat>
 #include <cmath>
 
 #include "../../include/hhlb.h"
@@ -48,7 +49,7 @@ int sturm_count(const Rule &r, int n, ld x) {
   for (int i = 0; i < n; ++i) {
     ld off2 = (i == 0) ? 0 : r.b[i];
     ld dn = (r.a[i] - x) - (i == 0 ? 0 : off2 / d);
-    if (dn == 0) dn = -1e-4000L;
+    if (dn == 0) dn = -LDBL_MIN;
     if (dn < 0) ++cnt;
     d = dn;
   }
@@ -288,7 +289,7 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
 // G^-_l follows with u -> -u.  Then g_k = w_k sum_{l<=N} G^sigma_l h_l(z_k).
 // Full range (Sec. IV.A.3): G_l = E[He_l(X)], X ~ N(ub, mT/p0^2), from
 // G_{l+1} = ub G_l + l (mT/p0^2 - 1) G_{l-1}; g_k = w_k sum G_l He_l(z_k)/l!.
-void equilibrium(const Rule &r, int N, ld u, ld T, double *g) {
+void equilibrium_nc(const Rule &r, int N, ld u, ld T, int nc, ld *g) {
   const int Q = r.Q, H = r.H;
   const ld m = 1, p0 = r.p0;
   if (r.quad == kFull) {
@@ -306,12 +307,12 @@ void equilibrium(const Rule &r, int N, ld u, ld T, double *g) {
         if (l > 0) fact *= l;
         acc += G[l] * h[l] / sqrtl(fact);
       }
-      g[k] = (double)(r.w[k % H] * acc);
+      g[k] = r.w[k % H] * acc;
     }
     return;
   }
   std::vector<ld> tau, lam;
-  gauss_legendre01(16, tau, lam);
+  if (nc > 0) gauss_legendre01(nc, tau, lam);
   ld ub = m * u / p0, s = sqrtl(m * T) / p0, y0 = -u * sqrtl(m / T);
   std::vector<ld> h(Q + 1), Gp(N + 1, 0), Gm(N + 1, 0);
   for (int j = 0; j < Q; ++j) {
@@ -321,7 +322,7 @@ void equilibrium(const Rule &r, int N, ld u, ld T, double *g) {
     for (int l = 0; l <= N; ++l) Gm[l] += r.w[j] * h[l];
   }
   if (y0 != 0) {
-    for (size_t i = 0; i < tau.size(); ++i) {
+    for (int i = 0; i < nc; ++i) {
       ld e = y0 * lam[i] * expl(-(y0 * tau[i]) * (y0 * tau[i]) / 2) / sqrtl(2 * kPi);
       ortho_values(r, N, ub * (1 - tau[i]), h.data());
       for (int l = 0; l <= N; ++l) Gp[l] -= e * h[l];
@@ -333,9 +334,43 @@ void equilibrium(const Rule &r, int N, ld u, ld T, double *g) {
     ortho_values(r, N, r.z[k], h.data());
     ld ap = 0, am = 0;
     for (int l = 0; l <= N; ++l) { ap += Gp[l] * h[l]; am += Gm[l] * h[l]; }
-    g[k] = (double)(r.w[k] * ap);
-    g[H + k] = (double)(r.w[k] * am);
+    g[k] = r.w[k] * ap;
+    g[H + k] = r.w[k] * am;
   }
+}
+
+void equilibrium(const Rule &r, int N, ld u, ld T, double *g) {
+  std::vector<ld> gl(r.V);
+  equilibrium_nc(r, N, u, T, 32, gl.data());
+  for (int k = 0; k < r.V; ++k) g[k] = (double)gl[k];
+}
+
+double correction_limit(const Rule &r, int N, int nc, double tol) {
+  if (r.quad != kHalf || nc <= 0) return 0.0;
+  const ld Ts[4] = {0.5L, 1.0L, 2.0L, 3.0L};
+  std::vector<ld> g(r.V), gr(r.V);
+  double best = 0.0;
+  for (int e = 0; e <= 96; ++e) {
+    ld y = 1e-6L * powl(10.0L, e / 16.0L);   // 1e-6 .. 1
+    bool ok = true;
+    for (ld T : Ts) {
+      for (int sgn = -1; sgn <= 1 && ok; sgn += 2) {
+        ld u = sgn * y * sqrtl(T);
+        equilibrium_nc(r, N, u, T, nc, g.data());
+        equilibrium_nc(r, N, u, T, 40, gr.data());
+        ld mx = 0, err = 0;
+        for (int k = 0; k < r.V; ++k) {
+          mx = std::max(mx, fabsl(gr[k]));
+          err = std::max(err, fabsl(g[k] - gr[k]));
+        }
+        if (err > tol * mx) ok = false;
+      }
+      if (!ok) break;
+    }
+    if (!ok) break;
+    best = (double)y;
+  }
+  return best;
 }
 
 }  // namespace hhlb

@@ -31,6 +31,14 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err);
 // Discrete equilibrium g_k(u, T) of order N (V values, n = 1), long double.
 void equilibrium(const Rule &r, int N, long double u, long double T, double *g);
 
+// Same, with the half-range correction integral taken with nc Gauss-Legendre
+// points (the form the kernels evaluate); g in long double.
+void equilibrium_nc(const Rule &r, int N, long double u, long double T, int nc, long double *g);
+
+// Largest |y0| = |u| sqrt(m/T) for which nc correction points keep the
+// half-range equilibrium within tol of max|g| (T in [0.5, 3]).
+double correction_limit(const Rule &r, int N, int nc, double tol);
+
 // Gauss-Legendre nodes tau_i in (0,1) and weights lam_i (sum 1), n points.
 void gauss_legendre01(int n, std::vector<long double> &tau, std::vector<long double> &lam);
 
