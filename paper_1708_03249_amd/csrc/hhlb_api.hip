@@ -345,6 +345,16 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
               for (int l = 0; l < h.Q; ++l)
                 d.HWs[k * h.Q + l] = l <= N ? (double)((long double)r.HW[(size_t)k * h.Q + l] * inv_norm[l]) : 0.0;
         }
+        // main rule of the half-range equilibrium: M = ceil((N+1)/2) points
+        if (h.quad == HHLB_HALF_HERMITE) {
+          const int M = (N + 2) / 2;
+          hhlb::Rule rm;
+          std::string err2;
+          int st2 = hhlb::build_rule(HHLB_HALF_HERMITE, M, 1.0, rm, err2);
+          if (st2) return fail(st2, "equilibrium rule: " + err2);
+          d.nm = M;
+          for (int j = 0; j < M; ++j) { d.zm[j] = (double)rm.z[j]; d.wm[j] = (double)rm.w[j]; }
+        }
         // correction ladder (half range): point counts and the |y0| each covers
         {
           const int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};

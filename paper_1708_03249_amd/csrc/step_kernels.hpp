@@ -39,6 +39,10 @@ struct DevTables {
   int lad_n[kLadder], lad_off[kLadder];
   double lad_y[kLadder];
   double ltau[kLadderPts], llamw[kLadderPts];
+  // main-part rule of the equilibrium: the M-point half-range Gauss rule,
+  // M = ceil((N+1)/2), exact for the degree-N integrands
+  int nm;
+  double zm[kQmaxDev], wm[kQmaxDev];
 };
 
 // Per channel.
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void s
       }
     };
 #pragma unroll 1
-    for (int j = 0; j < Q; ++j) accum(ub + s * tb->z[j], tb->w[j]);
+    for (int j = 0; j < tb->nm; ++j) accum(ub + s * tb->zm[j], tb->wm[j]);
     // correction over [y0, 0]: the smallest ladder entry that covers the wave
     const double ymax = wave_max(inside ? fabs(y0) : 0.0);
     if (ymax > 0.0) {
