@@ -59,6 +59,24 @@ def flops_per_node_update(Q=Q, N=Q - 1, nfun=2, nc=8):
     return 3 * (nfun * per_node_fn + per_cell / V)
 
 
+def measured_traffic():
+    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes, if they were taken on the kernel source built now."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for f in ("step_kernels.hpp", "hhlb_api.hip"):
+        with open(os.path.join(ROOT, "paper_1708_03249_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def cpu_baseline(n_channels, steps):
     """Time the plain CPU oracle on a bounded sample of the same workload:
     n_channels channels (one thread each) for `steps` RK-3 steps."""
@@ -99,7 +117,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        import torch
+        n = args.copy_probe_mib * 2**20 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": n * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "channels are independent and would shard across GPUs without exchange, "
@@ -146,13 +177,15 @@ def main():
     hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tfs / FP64_VECTOR_PEAK_TFLOPS
     if hbm_frac >= alu_frac:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_frac, 4), "traffic": None}
+                "frac": round(hbm_frac, 4), "traffic": measured_traffic()}
         other = {"alu_fp64_tflops": round(tfs, 2), "alu_frac": round(alu_frac, 4)}
     else:
         roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": None}
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": measured_traffic()}
         other = {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4)}
-    roof["kernel"] = "hhlb::stage_kernel<0,16,2,0> (one RK-3 stage, FP64)"
+    roof["kernel"] = "hhlb::stage_kernel_half<16,2,0> (one RK-3 stage, FP64)"
+    roof["algorithmic_bytes_per_launch"] = bpl
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)"
     roof["avg_launch_us"] = round(avg_launch_s * 1e6, 2)
     roof.update(other)
     out = {

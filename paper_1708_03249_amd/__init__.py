@@ -17,7 +17,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhhlb.so")
+# HHLB_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("HHLB_LIBRARY") or os.path.join(_HERE, "libhhlb.so")
 
 HALF_HERMITE, FULL_HERMITE = 0, 1
 WENO5, UPWIND3 = 0, 1

@@ -27,23 +27,26 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, out: str | None = None, defines=()) -> str:
+    """Compile libhhlb.so (or `out`); `defines` are extra -D tuning switches."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build" + ("_" + "_".join(defines) if defines else ""))
     os.makedirs(objdir, exist_ok=True)
     objs = []
     for src, extra in (("tables.cpp", []), ("hhlb_api.hip", [])):
         obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc] + HIP_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + HIP_FLAGS + [f"-D{d}" for d in defines] + extra + [
+            "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):  # host-only code: plain C++ compiler
             cmd = [os.environ.get("CXX", "g++"), "-O2", "-std=c++17", "-fPIC", "-c",
                    os.path.join(CSRC, src), "-o", obj]
         _run(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    target = out or LIB
+    tmp = target + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

@@ -18,6 +18,15 @@ constexpr int kNc = 8;         // Gauss-Legendre points of the full-range kernel
 constexpr int kLadder = 8;     // correction point counts the half-range kernel chooses from
 constexpr int kLadderPts = 64; // total points over the ladder
 constexpr int kWin = 58;       // output cells per wavefront
+
+// Build-time tuning switches of the half-range kernel: matrix cores for the
+// two 16 x 16 contractions (Q = 16) and the occupancy target.
+#ifndef HHLB_MFMA
+#define HHLB_MFMA 1
+#endif
+#ifndef HHLB_HALF_WAVES
+#define HHLB_HALF_WAVES 3
+#endif
 constexpr int kHalo = 3;
 
 // Per model class (quadrature, Q, N, p0): uploaded once.
@@ -427,13 +436,50 @@ __device__ __forceinline__ double wave_max(double x) {
   return x;
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Register layout of v_mfma_f64_16x16x4f64 (checked on the GPU):
+//   A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+//   D[i][j] in lane j + 16 (i % 4), accumulator register i / 4.
+// OUT[i][cell] = sum_k M[i][k] X[k][cell] for the 16 x 16 table M (held as
+// four A operands, aM[kc] = M[lane % 16][4 kc + lane / 16]) and the 16
+// values X[0..15] each lane (= cell) holds.  The cell-major data are
+// transposed into the B layout and back through a padded LDS tile T of
+// 64 x 17 doubles owned by this wavefront.
+__device__ __forceinline__ void mfma_contract16(const double aM[4], const double X[16], double OUT[16],
+                                                double *T, int lane) {
+  constexpr int S = 17;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) T[lane * S + k] = X[k];
+  __builtin_amdgcn_wave_barrier();
+  dbl4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    acc[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const double b = T[(16 * cb + (lane & 15)) * S + 4 * kc + (lane >> 4)];
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aM[kc], b, acc[cb], 0, 0, 0);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[(16 * cb + (lane & 15)) * S + 4 * r + (lane >> 4)] = acc[cb][r];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) OUT[k] = T[lane * S + k];
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Half-range kernel: the two momentum halves of a window run in the two
 // wavefronts of a 128-thread block (wave 0: p > 0, wave 1: p < 0).  Each lane
 // holds the Q nodes of its half for f and chi; the only coupling between the
 // halves -- moment sums, the rank-1 cross term of the force matrix and the
 // wall densities -- goes through 6 KB of LDS and one barrier.
 template <int Q, int NFUN, int ADV>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel_half(
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_WAVES))) void stage_kernel_half(
     StageArgs A, const DevTables *__restrict__ tb, const DevChannel *__restrict__ chans,
     const DevWindow *__restrict__ wins, const double *__restrict__ inv_dx,
     const double *__restrict__ gw, const double *__restrict__ in_f,
@@ -442,6 +488,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void s
   constexpr int NC = NFUN;
   __shared__ double s_part[2][6][64];
   __shared__ double s_nw[2];
+  constexpr bool kMfma = HHLB_MFMA && (H == 16);   // matrix cores for the 16 x 16 contractions
+  __shared__ double s_T[kMfma ? 2 * 64 * 17 : 1];
   const int hw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int w = xcd_window(blockIdx.x, A.nwin);
@@ -601,38 +649,59 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void s
   const double gforce = C.g, dt = C.dt;
   const bool wall_face = hw == 0 ? (i == -1) : (i == Nx - 1);
 
-  // pass 1: equilibrium populations of this half
-  double geq[H];
-#pragma unroll
-  for (int j = 0; j < H; ++j) {
-    double acc = 0.0;
-#pragma unroll
-    for (int l = 0; l < Q; ++l) acc += tb->HWs[j * Q + l] * G[l];
-    geq[j] = acc;
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  // pass 2: local source -F (K y)_k - (y_k - y^eq_k)/tau for f and chi
+  // pass 1: local source -F (K y)_k - (y_k - y^eq_k)/tau for f and chi,
+  // with the equilibrium population g_k of this half
   double srcf[H], srcc[NC > 1 ? H : 1];
   const double eqc = C.half_Dt * T;
+  if constexpr (kMfma) {
+    // (K_in y) and (HWs G) as 16 x 16 x 64-cell products on the matrix cores
+    double *Tw = s_T + hw * 64 * 17;
+    double aK[4], aH[4];
 #pragma unroll
-  for (int j = 0; j < H; ++j) {
-    double kf = 0.0, kc = 0.0;
-#pragma unroll
-    for (int jj = 0; jj < H; ++jj) {
-      const double kv = tb->Kin[j * H + jj];
-      kf += kv * yf[jj];
-      if constexpr (NC > 1) kc += kv * yc[jj];
+    for (int kc = 0; kc < 4; ++kc) {
+      aK[kc] = tb->Kin[(lane & 15) * H + 4 * kc + (lane >> 4)];
+      aH[kc] = tb->HWs[(lane & 15) * Q + 4 * kc + (lane >> 4)];
     }
-    kf = sg * (kf + tb->ka[j] * bf);
-    const double feq = n * geq[j];
-    srcf[j] = -gforce * kf - (collide ? (yf[j] - feq) * inv_tau : 0.0);
+    double geq[H], ky[H];
+    mfma_contract16(aH, G, geq, Tw, lane);
+    mfma_contract16(aK, yf, ky, Tw, lane);
+#pragma unroll
+    for (int j = 0; j < H; ++j)
+      srcf[j] = -gforce * sg * (ky[j] + tb->ka[j] * bf) - (yf[j] - n * geq[j]) * inv_tau;
     if constexpr (NC > 1) {
-      kc = sg * (kc + tb->ka[j] * bc);
-      srcc[j] = -gforce * kc - (collide ? (yc[j] - eqc * feq) * inv_tau : 0.0);
+      mfma_contract16(aK, yc, ky, Tw, lane);
+#pragma unroll
+      for (int j = 0; j < H; ++j)
+        srcc[j] = -gforce * sg * (ky[j] + tb->ka[j] * bc) - (yc[j] - eqc * n * geq[j]) * inv_tau;
     }
-    __builtin_amdgcn_sched_barrier(0);
+  } else {
+    double geq[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) acc += tb->HWs[j * Q + l] * G[l];
+      geq[j] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      double kf = 0.0, kc = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < H; ++jj) {
+        const double kv = tb->Kin[j * H + jj];
+        kf += kv * yf[jj];
+        if constexpr (NC > 1) kc += kv * yc[jj];
+      }
+      kf = sg * (kf + tb->ka[j] * bf);
+      const double feq = n * geq[j];
+      srcf[j] = -gforce * kf - (yf[j] - feq) * inv_tau;   // inv_tau = 0 when collisionless
+      if constexpr (NC > 1) {
+        kc = sg * (kc + tb->ka[j] * bc);
+        srcc[j] = -gforce * kc - (yc[j] - eqc * feq) * inv_tau;
+      }
+    }
   }
-  // pass 3: advection (WENO-5 / upwind-3 face fluxes, Sec. IV.C.2) and the
+  // pass 2: advection (WENO-5 / upwind-3 face fluxes, Sec. IV.C.2) and the
   // RK-3 combination
 #pragma unroll
   for (int j = 0; j < H; ++j) {
