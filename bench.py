@@ -61,7 +61,8 @@ def flops_per_node_update(Q=Q, N=Q - 1, nfun=2, nc=8):
 
 def measured_traffic():
     """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes, if they were taken on the kernel source built now."""
+    WRITE_SIZE passes, if they were taken on the kernel source (the stage
+    kernel's header and the build flags) built now."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
     if not os.path.exists(path):
@@ -69,8 +70,8 @@ def measured_traffic():
     with open(path) as fh:
         rec = json.load(fh)
     h = hashlib.sha256()
-    for f in ("step_kernels.hpp", "hhlb_api.hip"):
-        with open(os.path.join(ROOT, "paper_1708_03249_amd", "csrc", f), "rb") as fh:
+    for f in rec.get("kernel_source_files", ()):
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest() != rec.get("kernel_source_sha256"):
         return None
@@ -116,7 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=8)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

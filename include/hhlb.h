@@ -128,8 +128,19 @@ hhlb_status hhlb_set_state(hhlb_solver *s, const double *f_dev, const double *ch
 /* Set f_k = n0 g_k(u0, T0) in every cell and chi_k = (Dt/2) T0 f_k. */
 hhlb_status hhlb_init_equilibrium(hhlb_solver *s, double n0, double u0, double T0);
 
-/* Advance every channel by n_steps TVD RK-3 steps (Eq. rk3).  Asynchronous. */
+/* Advance every channel by n_steps TVD RK-3 steps (Eq. rk3).  Asynchronous:
+ * ordered after the work already on the solver's stream and before work
+ * enqueued there later.  By default every stage kernel is launched directly
+ * on the solver's stream; hhlb_set_graph_steps switches to HIP graph replay. */
 hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps);
+
+/* Steps captured per HIP graph (default 0 = direct launches on the solver's
+ * stream).  With steps_per_graph > 0, hhlb_step replays graphs of that many
+ * steps (and a 1-step graph for the remainder) on an internal stream of
+ * default priority, ordered against the solver's stream by events; results
+ * are bit-identical to direct launches.  Graphs are rebuilt on the next step.
+ * steps_per_graph < 0 is HHLB_E_ARG. */
+hhlb_status hhlb_set_graph_steps(hhlb_solver *s, int32_t steps_per_graph);
 
 /* Copy the state out (device pointers, boundary layout).  chi_dev may be
  * NULL.  Asynchronous on the stream. */

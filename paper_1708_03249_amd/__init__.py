@@ -101,11 +101,12 @@ def lib():
         L.hhlb_diagnostics.argtypes = [vp, vp, vp, vp]
         L.hhlb_launch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.hhlb_destroy.argtypes = [vp]
+        L.hhlb_set_graph_steps.argtypes = [vp, i32]
         for name in ("hhlb_nodes", "hhlb_force_matrix", "hhlb_equilibrium", "hhlb_create",
                      "hhlb_workspace_bytes", "hhlb_bind_workspace", "hhlb_state_offsets",
                      "hhlb_time_steps", "hhlb_set_state", "hhlb_init_equilibrium", "hhlb_step",
                      "hhlb_get_state", "hhlb_moments", "hhlb_diagnostics", "hhlb_launch_info",
-                     "hhlb_destroy"):
+                     "hhlb_destroy", "hhlb_set_graph_steps"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -194,6 +195,10 @@ class Solver:
 
     def step(self, n_steps: int):
         _check(lib().hhlb_step(self.h, int(n_steps)))
+
+    def set_graph_steps(self, steps_per_graph: int):
+        """Steps per replayed HIP graph; 0 = direct launches."""
+        _check(lib().hhlb_set_graph_steps(self.h, int(steps_per_graph)))
 
     def moments(self):
         t = self.torch

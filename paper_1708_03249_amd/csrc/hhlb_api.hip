@@ -181,6 +181,18 @@ struct hhlb_solver {
          o_nwall = 0, o_feq = 0, o_feqoff = 0, o_state = 0, bytes = 0;
   char *ws = nullptr;
   double *fA = nullptr, *fB = nullptr, *fC = nullptr, *cA = nullptr, *cB = nullptr, *cC = nullptr;
+  // graph replay of the step sequence (0 = direct launches)
+  int graph_steps = 0;   // direct launches: measured no slower than graph replay
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gexec_k = nullptr, gexec_1 = nullptr;
+  ~hhlb_solver() {
+    if (gexec_k) (void)hipGraphExecDestroy(gexec_k);
+    if (gexec_1) (void)hipGraphExecDestroy(gexec_1);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
+  }
 };
 
 namespace {
@@ -503,6 +515,8 @@ hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr) {
   HIP_TRY(hipMemsetAsync(ws + s->o_nwall, 0, sizeof(double) * 2 * n_ch, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->ws = ws;
+  if (s->gexec_k) { (void)hipGraphExecDestroy(s->gexec_k); s->gexec_k = nullptr; }
+  if (s->gexec_1) { (void)hipGraphExecDestroy(s->gexec_1); s->gexec_1 = nullptr; }
   double *st = (double *)(ws + s->o_state);
   const size_t stride = align256(sizeof(double) * s->total_state) / sizeof(double);
   s->fA = st; s->fB = st + stride; s->fC = st + 2 * stride;
@@ -571,10 +585,12 @@ hhlb_status hhlb_init_equilibrium(hhlb_solver *s, double n0, double u0, double T
   return HHLB_OK;
 }
 
-hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
-  if (!s) return fail(HHLB_E_ARG, "null solver");
-  if (n_steps < 0) return fail(HHLB_E_ARG, "n_steps must be >= 0");
-  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+}  // extern "C"
+
+namespace {
+
+// Enqueue n_steps RK-3 steps (three stage launches per model class each).
+void enqueue_steps(hhlb_solver *s, int64_t n_steps, hipStream_t stream) {
   const double ab[3] = {0.0, 0.75, 1.0 / 3.0};
   const double bs[3] = {1.0, 0.25, 2.0 / 3.0};
   for (int64_t step = 0; step < n_steps; ++step) {
@@ -599,13 +615,68 @@ hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
         a.a_base = ab[stage];
         a.b_stage = bs[stage];
         a.nwall = (double *)(s->ws + s->o_nwall);
-        mc.launch(a, s->stream);
+        mc.launch(a, stream);
       }
     }
   }
-  HIP_TRY(hipGetLastError());
+}
+
+hhlb_status make_graph(hhlb_solver *s, int64_t steps, hipGraphExec_t *out) {
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal));
+  enqueue_steps(s, steps, s->gstream);
+  hipError_t e = hipStreamEndCapture(s->gstream, &g);
+  if (e != hipSuccess) return fail(HHLB_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(HHLB_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   return HHLB_OK;
 }
+
+}  // namespace
+
+extern "C" hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
+  if (!s) return fail(HHLB_E_ARG, "null solver");
+  if (n_steps < 0) return fail(HHLB_E_ARG, "n_steps must be >= 0");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  if (n_steps == 0) return HHLB_OK;
+  if (s->graph_steps <= 0) {
+    enqueue_steps(s, n_steps, s->stream);
+    HIP_TRY(hipGetLastError());
+    return HHLB_OK;
+  }
+  // graph replay on an internal stream, ordered after the caller's stream
+  // and before whatever the caller enqueues next
+  if (!s->gstream) {
+    HIP_TRY(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
+  }
+  if (!s->gexec_k) {
+    hhlb_status st = make_graph(s, s->graph_steps, &s->gexec_k);
+    if (st) return st;
+    st = make_graph(s, 1, &s->gexec_1);
+    if (st) return st;
+  }
+  HIP_TRY(hipEventRecord(s->ev_in, s->stream));
+  HIP_TRY(hipStreamWaitEvent(s->gstream, s->ev_in, 0));
+  const int64_t full = n_steps / s->graph_steps, rest = n_steps % s->graph_steps;
+  for (int64_t r = 0; r < full; ++r) HIP_TRY(hipGraphLaunch(s->gexec_k, s->gstream));
+  for (int64_t r = 0; r < rest; ++r) HIP_TRY(hipGraphLaunch(s->gexec_1, s->gstream));
+  HIP_TRY(hipEventRecord(s->ev_out, s->gstream));
+  HIP_TRY(hipStreamWaitEvent(s->stream, s->ev_out, 0));
+  return HHLB_OK;
+}
+
+extern "C" hhlb_status hhlb_set_graph_steps(hhlb_solver *s, int32_t steps_per_graph) {
+  if (!s || steps_per_graph < 0) return fail(HHLB_E_ARG, "need a solver and steps_per_graph >= 0");
+  if (s->gexec_k) { (void)hipGraphExecDestroy(s->gexec_k); s->gexec_k = nullptr; }
+  if (s->gexec_1) { (void)hipGraphExecDestroy(s->gexec_1); s->gexec_1 = nullptr; }
+  s->graph_steps = steps_per_graph;
+  return HHLB_OK;
+}
+
+extern "C" {
 
 hhlb_status hhlb_moments(const hhlb_solver *s, double *n_dev, double *u_dev, double *T_dev) {
   if (!s || !n_dev || !u_dev || !T_dev) return fail(HHLB_E_ARG, "null argument");

@@ -119,3 +119,121 @@ def test_mass_conservation_long():
     states = initial_states([ch])
     gpu = run_gpu([ch], states, 3000)
     assert abs(gpu["mass"][0] - 1.0) < 1e-12
+
+
+def test_graph_replay_matches_direct_launches():
+    """The HIP-graph replay of hhlb_step gives the same bits as direct
+    launches: several calls of 7 steps (less than one 16-step graph, so the
+    1-step graph runs too) and of 37 steps, with eager reads of the state and
+    synchronisations between the calls."""
+    import torch
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=8, Nx=200, adv=h.WENO5, stretch_A=0.9,
+                       T_left=1.0, T_right=2.0, g=-0.5, Kn=kn, dt=-0.5) for kn in (0.02, 0.5)]
+    states = initial_states(chans, seed=3, perturb=0.05)
+    f0 = torch.from_numpy(np.concatenate([s[0].ravel() for s in states])).cuda()
+    c0 = torch.from_numpy(np.concatenate([s[1].ravel() for s in states])).cuda()
+    solvers = []
+    for gsteps in (0, 16, 5):
+        s = h.Solver(chans)
+        s.set_graph_steps(gsteps)
+        s.set_state(f0, c0)
+        solvers.append(s)
+    for rnd, n in enumerate((7, 7, 37, 1, 16)):
+        outs = []
+        for s in solvers:
+            s.step(n)
+            f, c = s.get_state()
+            torch.cuda.synchronize()
+            outs.append((f.cpu().numpy(), c.cpu().numpy()))
+        for k in (1, 2):
+            assert np.array_equal(outs[0][0], outs[k][0]), f"f differs, call {rnd}, solver {k}"
+            assert np.array_equal(outs[0][1], outs[k][1]), f"chi differs, call {rnd}, solver {k}"
+    for s in solvers:
+        s.close()
+
+
+def _load_golden(path):
+    rows = {"f": [], "chi": []}
+    nwall = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            tag, *vals = line.split()
+            if tag == "nwall":
+                nwall = np.array([float(v) for v in vals])
+            else:
+                rows[tag].append([float(v) for v in vals])
+    return np.array(rows["f"]), np.array(rows["chi"]), nwall
+
+
+def test_small_channel_20000_steps_golden():
+    """HHLB(3;4), Nx = 64, third-order upwind, Kn = 0.1, g = -0.1, equal walls,
+    dt = 5e-4: 20 000 steps (t = 10, close to the steady flow) against the
+    stored oracle result (tests/golden/small_channel_20000.txt, written by
+    make_oracle_golden.py from the oracle alone)."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    fg, cg, nwg = _load_golden(os.path.join(here, "golden", "small_channel_20000.txt"))
+    h = H()
+    ch = h.Channel(quad=h.HALF_HERMITE, Q=4, N=3, Nx=64, adv=h.UPWIND3, transverse_dof=2,
+                   Kn=0.1, g=-0.1, dt=5e-4)
+    states = initial_states([ch])
+    print("[parity] small channel, 20000 steps", flush=True)
+    gpu = run_gpu([ch], states, 20000)
+    f = gpu["f"].reshape(ch.V, ch.Nx)
+    c = gpu["chi"].reshape(ch.V, ch.Nx)
+    ef = np.max(np.abs(f - fg) / np.abs(fg).max(axis=0, keepdims=True))
+    ec = np.max(np.abs(c - cg) / np.abs(cg).max(axis=0, keepdims=True))
+    en = np.max(np.abs(gpu["nw"][0] / nwg - 1))
+    assert max(ef, ec, en) <= TOL, (ef, ec, en)
+
+
+def test_bench_size_sampled_channels():
+    """The benchmark configuration at full size (256 channels x Nx = 16384,
+    HHLB(15;16), WENO-5, f and chi, stretched A = 0.9, CFL 0.5, graph
+    replay): 3 steps of the whole batch on the GPU; channels 0, 137 and 255
+    (first, interior, last) against the oracle."""
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    chans = bench.workload()
+    h = H()
+    s = h.Solver(chans)
+    s.init_equilibrium(1.0, 0.0, 1.0)
+    print("[parity] bench size, 256 x 16384, 3 steps", flush=True)
+    s.step(3)
+    f, c = s.get_state()
+    n, u, T = s.moments()
+    nw, mass, bad = s.diagnostics()
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    which = (0, 137, 255)
+    gpu = dict(offsets=np.zeros(len(chans) + 1, dtype=np.int64), cells=np.zeros(len(chans) + 1,
+               dtype=np.int64), f=[], chi=[], n=[], u=[], T=[], nw=np.zeros((len(chans), 2)))
+    # pack the sampled channels contiguously so compare() can index them
+    sub = [chans[w] for w in which]
+    off, cel = [0], [0]
+    for w, ch in zip(which, sub):
+        gpu["f"].append(s.channel_view(f, w).cpu().numpy().ravel())
+        gpu["chi"].append(s.channel_view(c, w).cpu().numpy().ravel())
+        a0, a1 = int(s.cells[w]), int(s.cells[w + 1])
+        for k, arr in (("n", n), ("u", u), ("T", T)):
+            gpu[k].append(arr[a0:a1].cpu().numpy())
+        off.append(off[-1] + ch.V * ch.Nx)
+        cel.append(cel[-1] + ch.Nx)
+    nwc = nw.cpu().numpy()
+    gpu["nw"] = np.array([nwc[w] for w in which])
+    for k in ("f", "chi", "n", "u", "T"):
+        gpu[k] = np.concatenate(gpu[k])
+    gpu["offsets"], gpu["cells"] = np.array(off), np.array(cel)
+    dts = [s.dt[w] for w in which]
+    s.close()
+    from gpu_common import to_oracle
+    import oracle as O
+    states = []
+    for ch in sub:
+        fo, co = O.initial_state(to_oracle(ch))
+        states.append((fo, co))
+    ref = run_oracle(sub, states, 3, dts)
+    compare(sub, gpu, ref, tol=TOL, what="bench size")
