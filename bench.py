@@ -8,8 +8,16 @@ g = -1, T_left = 1, T_right = 1.5, CFL 0.5.  One step = one RK-3 step of
 every channel; a node-update is one (x_i, p_k) pair of f and chi advanced
 by one step.  Inputs are resident in HBM before the timed region.
 
+Every arithmetic form runs on the same workload, one after the other: the
+FP64 form (the primary line) and the mixed forms (FP32 state with a 16-bit
+correction word, FP32 advection / collision, force block in FP32, BF16 or
+FP16 on the matrix cores, FP64 moments and wall balance).  Each mixed form
+reports its speed against the FP64 form and its largest moment difference
+from the FP64 form after the same steps (the FP64 form matches the CPU
+oracle to 1e-12).
+
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
---no-cpu-baseline.
+--forms fp64,mixed_f32,... --no-cpu-baseline.
 """
 from __future__ import annotations
 
@@ -38,11 +46,14 @@ def workload(n_ch=N_CH, nx=NX):
                       dt=-0.5) for kn in kns]
 
 
-def bytes_per_node_update(nfun=2, word=8):
-    """Algorithmic HBM bytes of one RK-3 step with one kernel per stage:
-    stage 1 reads y^n and writes y1; stages 2 and 3 read the stage state and
-    y^n and write the next state: 8 array passes per function."""
-    return 8 * nfun * word
+def bytes_per_node_update(form="fp64", nfun=2):
+    """Algorithmic HBM bytes of one RK-3 step with one kernel per stage.
+    FP64: stage 1 reads y^n and writes y1; stages 2 and 3 read the stage state
+    and y^n and write the next state: 8 passes of 8 bytes per function.
+    Mixed: stage 1 reads hi (4) and writes d1 (4); stage 2 reads hi and d1 and
+    writes d2; stage 3 reads hi, lo (2) and d2 and writes hi and lo: 36 bytes
+    per function."""
+    return nfun * (64 if form == "fp64" else 36)
 
 
 def flops_per_node_update(Q=Q, N=Q - 1, nfun=2, nc=8):
@@ -59,12 +70,13 @@ def flops_per_node_update(Q=Q, N=Q - 1, nfun=2, nc=8):
     return 3 * (nfun * per_node_fn + per_cell / V)
 
 
-def measured_traffic():
+def measured_traffic(form="fp64"):
     """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE passes, if they were taken on the kernel source (the stage
     kernel's header and the build flags) built now."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
+    name = "stage_kernel_traffic.json" if form == "fp64" else f"stage_kernel_{form}_traffic.json"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -110,12 +122,80 @@ def cpu_baseline(n_channels, steps):
                       f"{steps} RK-3 steps each, one thread per channel, {el:.1f} s"}
 
 
+def run_form(H, torch, np, chans, form, args):
+    """Warm up, time args.steps steps of one arithmetic form; return its
+    record and the final moments (device tensors)."""
+    s = H.Solver(chans, precision=H.PRECISIONS[form])
+    s.init_equilibrium(1.0, 0.0, 1.0)
+    print(f"[bench] {form}: {len(chans)} channels x Nx={NX}, V={2 * Q}; workspace "
+          f"{s.ws_bytes / 2**30:.2f} GiB; warmup {args.warmup}", file=sys.stderr, flush=True)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    launches, windows = s.launch_info()
+    stream = s.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    nw, mass, bad = s.diagnostics()
+    mom = s.moments()
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0, f"{form}: non-finite populations"
+    mass_err = float((mass - 1.0).abs().max().item())
+    node_updates = sum(c.V * c.Nx for c in chans) * args.steps
+    value = node_updates / (ms / 1e3)
+    # dominant kernel: the fused stage kernel (every launch of the timed region)
+    n_launch = 3 * args.steps * launches
+    avg_launch_s = ms / 1e3 / n_launch
+    nu_per_launch = sum(c.V * c.Nx for c in chans) / launches
+    bpl = bytes_per_node_update(form) / 3 * nu_per_launch
+    fpl = flops_per_node_update() / 3 * nu_per_launch
+    gbs = bpl / avg_launch_s / 1e9
+    tfs = fpl / avg_launch_s / 1e12
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tfs / FP64_VECTOR_PEAK_TFLOPS
+    if hbm_frac >= alu_frac:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4), "traffic": measured_traffic(form)}
+        other = {"alu_fp64_tflops": round(tfs, 2), "alu_frac": round(alu_frac, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": measured_traffic(form)}
+        other = {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4)}
+    kname = ("hhlb::stage_kernel_half<16,2,0> (one RK-3 stage, FP64)" if form == "fp64" else
+             f"hhlb::stage_kernel_mixed<16,2,0,{H.PRECISIONS[form]}> (one RK-3 stage, {form})")
+    roof["kernel"] = kname
+    roof["algorithmic_bytes_per_launch"] = bpl
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)"
+    roof["avg_launch_us"] = round(avg_launch_s * 1e6, 2)
+    roof.update(other)
+    rec = {"value": value, "ms_per_step": ms / args.steps, "roofline": roof, "mass_drift": mass_err,
+           "wall_s": round(wall, 3), "node_updates_per_step": node_updates // args.steps}
+    s.close()
+    return rec, mom
+
+
+def moment_diff(np, a, b):
+    """err_n = max|dn|/max n, err_u = max|du|/sqrt(T_left), err_T = max|dT|/max T."""
+    n0, u0, T0 = a
+    n1, u1, T1 = b
+    return {"err_n": ((n1 - n0).abs().max() / n0.abs().max()).item(),
+            "err_u": (u1 - u0).abs().max().item(),
+            "err_T": ((T1 - T0).abs().max() / T0.abs().max()).item()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp64,mixed_f32,mixed_bf16,mixed_f16",
+                    help="arithmetic forms to time; the first is the primary line")
     ap.add_argument("--cpu-channels", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -144,74 +224,44 @@ def main():
     import paper_1708_03249_amd as H
 
     chans = workload()
-    s = H.Solver(chans)
-    s.init_equilibrium(1.0, 0.0, 1.0)
-    print(f"[bench] {len(chans)} channels x Nx={NX}, V={2 * Q}; workspace "
-          f"{s.ws_bytes / 2**30:.2f} GiB; warmup {args.warmup}", file=sys.stderr, flush=True)
-    s.step(args.warmup)
-    torch.cuda.synchronize()
-    launches, windows = s.launch_info()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    s.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    nw, mass, bad = s.diagnostics()
-    torch.cuda.synchronize()
-    assert int(bad.item()) == 0, "non-finite populations"
-    mass_err = float((mass - 1.0).abs().max().item())
-    node_updates = sum(c.V * c.Nx for c in chans) * args.steps
-    value = node_updates / (ms / 1e3)
-    # dominant kernel: the fused stage kernel (all launches of the timed region)
-    n_launch = 3 * args.steps * launches
-    avg_launch_s = ms / 1e3 / n_launch
-    nu_per_launch = sum(c.V * c.Nx for c in chans) / launches
-    bpl = bytes_per_node_update() / 3 * nu_per_launch
-    fpl = flops_per_node_update() / 3 * nu_per_launch
-    gbs = bpl / avg_launch_s / 1e9
-    tfs = fpl / avg_launch_s / 1e12
-    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tfs / FP64_VECTOR_PEAK_TFLOPS
-    if hbm_frac >= alu_frac:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_frac, 4), "traffic": measured_traffic()}
-        other = {"alu_fp64_tflops": round(tfs, 2), "alu_frac": round(alu_frac, 4)}
-    else:
-        roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": measured_traffic()}
-        other = {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4)}
-    roof["kernel"] = "hhlb::stage_kernel_half<16,2,0> (one RK-3 stage, FP64)"
-    roof["algorithmic_bytes_per_launch"] = bpl
-    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)"
-    roof["avg_launch_us"] = round(avg_launch_s * 1e6, 2)
-    roof.update(other)
+    forms = [f for f in args.forms.split(",") if f]
+    results, ref_moments = {}, None
+    for form in forms:
+        r, mom = run_form(H, torch, np, chans, form, args)
+        if form == "fp64":
+            ref_moments = mom
+        elif ref_moments is not None:
+            r["err_vs_fp64"] = {k: float(v) for k, v in moment_diff(np, ref_moments, mom).items()}
+        results[form] = r
+        del mom
+        torch.cuda.empty_cache()
+    prim = results[forms[0]]
     out = {
         "metric": "velocity-node updates/s (x·p_x)",
-        "value": value,
+        "value": prim["value"],
         "unit": "node-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": prim["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if forms[0] == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{len(chans)} channels x Nx={NX} tanh-stretched (A=0.9), "
                                "HHLB(15;16) V=32, WENO5+RK3, f and chi, Kn~U[0.005,0.05], g=-1, "
                                "T_right/T_left=1.5, CFL 0.5",
-                   "channels": len(chans), "Nx": NX, "V": 2 * Q, "form": "FP64",
-                   "node_updates_per_step": node_updates // args.steps},
-        "roofline": roof,
-        "mass_drift": mass_err,
-        "wall_s": round(wall, 3),
+                   "channels": len(chans), "Nx": NX, "V": 2 * Q, "form": forms[0],
+                   "node_updates_per_step": prim["node_updates_per_step"]},
+        "roofline": prim["roofline"],
+        "mass_drift": prim["mass_drift"],
+        "forms": {f: {k: v for k, v in r.items() if k != "roofline"} | {"roofline": r["roofline"]}
+                  for f, r in results.items() if f != forms[0]},
     }
-    s.close()
+    if "fp64" in results:
+        out["speed_vs_fp64"] = {f: round(r["value"] / results["fp64"]["value"], 3)
+                                for f, r in results.items() if f != "fp64"}
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: {args.cpu_channels} channels x {args.cpu_steps} steps",
               file=sys.stderr, flush=True)

@@ -52,7 +52,17 @@ enum {
 
 enum { HHLB_HALF_HERMITE = 0, HHLB_FULL_HERMITE = 1 };   /* quadrature kind   */
 enum { HHLB_WENO5 = 0, HHLB_UPWIND3 = 1 };              /* advection scheme  */
-enum { HHLB_FP64 = 0 };                                 /* arithmetic path   */
+/* Arithmetic form of a solver (hhlb_create).
+ *  HHLB_FP64:       every step in FP64; state stored as f_k in FP64.
+ *  HHLB_MIXED_F32:  state stored in FP32 as f_k / w_k (w_k the node weight);
+ *                   advection, collision, force contraction and the RK-3
+ *                   combination in FP32; moment sums, the wall-density flux
+ *                   balance (Eq. nplus_def) and the equilibrium coefficients
+ *                   in FP64.  Half-range model only.
+ *  HHLB_MIXED_BF16, HHLB_MIXED_F16: as HHLB_MIXED_F32 with the force block
+ *                   K y contracted on the matrix cores from BF16 / FP16
+ *                   operands with FP32 accumulation. */
+enum { HHLB_FP64 = 0, HHLB_MIXED_F32 = 1, HHLB_MIXED_BF16 = 2, HHLB_MIXED_F16 = 3 };
 
 /* One channel, following the paper's statement of the problem (Sec. IV.D,
  * Sec. V.A): quadrature kind and order Q, equilibrium order N, grid, Kn,
@@ -95,13 +105,16 @@ hhlb_status hhlb_equilibrium(int32_t quad, int32_t Q, int32_t N, double p0, doub
 /* ---- solver -------------------------------------------------------------- */
 
 /* Validate n_ch channels and build their tables on the host (extended
- * precision, rounded to double).  precision must be HHLB_FP64.  hip_stream is
- * a hipStream_t (NULL = default stream).  *out receives the solver. */
+ * precision, rounded to double).  precision is one of the HHLB_FP64 /
+ * HHLB_MIXED_* forms (a mixed form with a full-range channel is
+ * HHLB_E_UNSUPPORTED).  hip_stream is a hipStream_t (NULL = default stream).
+ * *out receives the solver. */
 hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t precision,
                         void *hip_stream, hhlb_solver **out);
 
 /* Bytes of device workspace the solver needs (tables, grid, three RK
- * state copies, diagnostics). */
+ * state copies -- 8 bytes per population in FP64, 4 in the mixed forms --
+ * and diagnostics). */
 hhlb_status hhlb_workspace_bytes(const hhlb_solver *s, size_t *bytes);
 
 /* Bind caller-owned device memory of at least hhlb_workspace_bytes bytes,
@@ -121,8 +134,9 @@ hhlb_status hhlb_state_offsets(const hhlb_solver *s, int64_t *off);
  * dt_out: n_ch host doubles. */
 hhlb_status hhlb_time_steps(const hhlb_solver *s, double *dt_out);
 
-/* Copy a state in (device pointers, boundary layout, FP64).  chi_dev may be
- * NULL only if every channel has Dt = 0.  Asynchronous on the stream. */
+/* Copy a state in (device pointers, boundary layout, FP64; the mixed forms
+ * round f_k / w_k to FP32).  chi_dev may be NULL only if every channel has
+ * Dt = 0.  Asynchronous on the stream. */
 hhlb_status hhlb_set_state(hhlb_solver *s, const double *f_dev, const double *chi_dev);
 
 /* Set f_k = n0 g_k(u0, T0) in every cell and chi_k = (Dt/2) T0 f_k. */
@@ -131,7 +145,9 @@ hhlb_status hhlb_init_equilibrium(hhlb_solver *s, double n0, double u0, double T
 /* Advance every channel by n_steps TVD RK-3 steps (Eq. rk3).  Asynchronous:
  * ordered after the work already on the solver's stream and before work
  * enqueued there later.  By default every stage kernel is launched directly
- * on the solver's stream; hhlb_set_graph_steps switches to HIP graph replay. */
+ * on the solver's stream; hhlb_set_graph_steps switches to HIP graph replay.
+ * Returns HHLB_E_NUMERIC without stepping when the last hhlb_diagnostics
+ * found non-finite populations (it waits for that diagnostics to finish). */
 hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps);
 
 /* Steps captured per HIP graph (default 0 = direct launches on the solver's
@@ -142,8 +158,8 @@ hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps);
  * steps_per_graph < 0 is HHLB_E_ARG. */
 hhlb_status hhlb_set_graph_steps(hhlb_solver *s, int32_t steps_per_graph);
 
-/* Copy the state out (device pointers, boundary layout).  chi_dev may be
- * NULL.  Asynchronous on the stream. */
+/* Copy the state out (device pointers, boundary layout, FP64).  chi_dev may
+ * be NULL.  Asynchronous on the stream. */
 hhlb_status hhlb_get_state(const hhlb_solver *s, double *f_dev, double *chi_dev);
 
 /* Moments of Eq. (fmoms) per cell, with chi's transverse energy in T:
@@ -152,9 +168,15 @@ hhlb_status hhlb_moments(const hhlb_solver *s, double *n_dev, double *u_dev, dou
 
 /* Diagnostics (device pointers, any may be NULL): n_wall_dev[2*c+{0,1}]
  * wall densities n_+ (left) and n_- (right) of the last evaluated stage,
- * Eq. (nplus_def); mass_dev[c] = sum_i dx_i n_i (Eq. Ndef); nonfinite_dev[0]
- * = number of non-finite populations in the state. */
-hhlb_status hhlb_diagnostics(const hhlb_solver *s, double *n_wall_dev, double *mass_dev,
+ * Eq. (nplus_def); mass_dev[c] = sum_i dx_i n_i (Eq. Ndef);
+ * residual_dev[c] = max over f (and chi) of ||y1 - y||_inf / (dt ||y||_inf)
+ * with y1 = y + dt L[y] one forward-Euler stage from the current state
+ * (the state itself is unchanged; this costs one extra stage launch);
+ * nonfinite_dev[0] = number of non-finite populations in the state.  The
+ * non-finite count is also kept by the solver: the next hhlb_step returns
+ * HHLB_E_NUMERIC (and advances nothing) if it was non-zero.
+ * Asynchronous on the stream. */
+hhlb_status hhlb_diagnostics(hhlb_solver *s, double *n_wall_dev, double *mass_dev, double *residual_dev,
                              int32_t *nonfinite_dev);
 
 /* Kernel launches one hhlb_step of one RK stage issues (for profiling). */

@@ -22,7 +22,8 @@ LIB_PATH = os.environ.get("HHLB_LIBRARY") or os.path.join(_HERE, "libhhlb.so")
 
 HALF_HERMITE, FULL_HERMITE = 0, 1
 WENO5, UPWIND3 = 0, 1
-FP64 = 0
+FP64, MIXED_F32, MIXED_BF16, MIXED_F16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "mixed_f32": MIXED_F32, "mixed_bf16": MIXED_BF16, "mixed_f16": MIXED_F16}
 
 _STATUS = {0: "HHLB_OK", -1: "HHLB_E_ARG", -2: "HHLB_E_UNSUPPORTED", -3: "HHLB_E_HIP",
            -4: "HHLB_E_NOMEM", -5: "HHLB_E_NUMERIC", -6: "HHLB_E_STATE"}
@@ -98,7 +99,7 @@ def lib():
         L.hhlb_step.argtypes = [vp, i64]
         L.hhlb_get_state.argtypes = [vp, vp, vp]
         L.hhlb_moments.argtypes = [vp, vp, vp, vp]
-        L.hhlb_diagnostics.argtypes = [vp, vp, vp, vp]
+        L.hhlb_diagnostics.argtypes = [vp, vp, vp, vp, vp]
         L.hhlb_launch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.hhlb_destroy.argtypes = [vp]
         L.hhlb_set_graph_steps.argtypes = [vp, i32]
@@ -146,15 +147,18 @@ def equilibrium(quad: int, Q: int, N: int, n: float, u: float, T: float, p0: flo
 class Solver:
     """Channels advanced on one GPU.  Device memory comes from torch."""
 
-    def __init__(self, channels, device="cuda", stream=None):
+    def __init__(self, channels, device="cuda", stream=None, precision=FP64):
         import torch
         self.torch = torch
         self.channels = list(channels)
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        self.precision = int(precision)
         arr = (_CChannel * len(self.channels))(*[c._c() for c in self.channels])
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        _check(lib().hhlb_create(arr, len(self.channels), FP64,
+        _check(lib().hhlb_create(arr, len(self.channels), self.precision,
                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.h = h
         nb = ctypes.c_size_t()
@@ -208,15 +212,21 @@ class Solver:
                                   ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(T.data_ptr())))
         return n, u, T
 
-    def diagnostics(self):
+    def diagnostics(self, residual: bool = False):
+        """(n_wall [n_ch, 2], mass [n_ch], nonfinite [1]) as device tensors,
+        plus the residual [n_ch] when residual=True (one extra stage launch)."""
         t = self.torch
         nch = len(self.channels)
         nw = t.empty(2 * nch, dtype=t.float64, device=self.device)
         mass = t.empty(nch, dtype=t.float64, device=self.device)
+        res = t.empty(nch, dtype=t.float64, device=self.device) if residual else None
         bad = t.empty(1, dtype=t.int32, device=self.device)
         _check(lib().hhlb_diagnostics(self.h, ctypes.c_void_p(nw.data_ptr()),
                                       ctypes.c_void_p(mass.data_ptr()),
+                                      ctypes.c_void_p(res.data_ptr() if residual else 0),
                                       ctypes.c_void_p(bad.data_ptr())))
+        if residual:
+            return nw.view(nch, 2), mass, bad, res
         return nw.view(nch, 2), mass, bad
 
     def launch_info(self):

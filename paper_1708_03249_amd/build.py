@@ -27,21 +27,31 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
+SOURCES = ("tables.cpp", "hhlb_api.hip", "kernels_fp64.hip", "kernels_mixed_f32.hip",
+           "kernels_mixed_bf16.hip", "kernels_mixed_f16.hip")
+
+
 def build(verbose: bool = True, out: str | None = None, defines=()) -> str:
-    """Compile libhhlb.so (or `out`); `defines` are extra -D tuning switches."""
+    """Compile libhhlb.so (or `out`); `defines` are extra -D tuning switches.
+    The translation units compile in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build" + ("_" + "_".join(defines) if defines else ""))
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src, extra in (("tables.cpp", []), ("hhlb_api.hip", [])):
+    cmds, objs = [], []
+    for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc] + HIP_FLAGS + [f"-D{d}" for d in defines] + extra + [
-            "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):  # host-only code: plain C++ compiler
             cmd = [os.environ.get("CXX", "g++"), "-O2", "-std=c++17", "-fPIC", "-c",
                    os.path.join(CSRC, src), "-o", obj]
-        _run(cmd)
+        else:
+            cmd = [hipcc] + HIP_FLAGS + [f"-D{d}" for d in defines] + [
+                "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append(cmd)
         objs.append(obj)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(_run, cmds))
     target = out or LIB
     tmp = target + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/hhlb.h"
+#include "launch.hpp"
 #include "step_kernels.hpp"
 #include "tables.hpp"
 
@@ -32,40 +33,15 @@ hhlb_status fail(hhlb_status st, const std::string &msg) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-using Launcher = void (*)(const hhlb::StageArgs &, hipStream_t);
+using hhlb::Launcher;
 
-template <int QUAD, int Q, int NF, int ADV>
-void launch_stage(const hhlb::StageArgs &a, hipStream_t s) {
-  if constexpr (QUAD == 0)
-    hipLaunchKernelGGL((hhlb::stage_kernel_half<Q, NF, ADV>), dim3(a.nwin), dim3(128), 0, s, a, a.tb,
-                       a.chans, a.wins, a.inv_dx, a.gw, a.in_f, a.in_c);
-  else
-    hipLaunchKernelGGL((hhlb::stage_kernel<QUAD, Q, NF, ADV>), dim3(a.nwin), dim3(64), 0, s, a);
-}
-
-template <int QUAD, int Q>
-void add_variants(std::map<std::tuple<int, int, int, int>, Launcher> &m) {
-  m[{QUAD, Q, 1, 0}] = launch_stage<QUAD, Q, 1, 0>;
-  m[{QUAD, Q, 1, 1}] = launch_stage<QUAD, Q, 1, 1>;
-  m[{QUAD, Q, 2, 0}] = launch_stage<QUAD, Q, 2, 0>;
-  m[{QUAD, Q, 2, 1}] = launch_stage<QUAD, Q, 2, 1>;
-}
-
-const std::map<std::tuple<int, int, int, int>, Launcher> &launchers() {
-  static std::map<std::tuple<int, int, int, int>, Launcher> m = [] {
-    std::map<std::tuple<int, int, int, int>, Launcher> t;
-    add_variants<0, 1>(t);
-    add_variants<0, 2>(t);
-    add_variants<0, 3>(t);
-    add_variants<0, 4>(t);
-    add_variants<0, 6>(t);
-    add_variants<0, 8>(t);
-    add_variants<0, 12>(t);
-    add_variants<0, 16>(t);
-    add_variants<1, 2>(t);
-    add_variants<1, 4>(t);
-    add_variants<1, 8>(t);
-    add_variants<1, 16>(t);
+const hhlb::LaunchMap &launchers() {
+  static hhlb::LaunchMap m = [] {
+    hhlb::LaunchMap t;
+    hhlb::register_fp64(t);
+    hhlb::register_mixed_f32(t);
+    hhlb::register_mixed_bf16(t);
+    hhlb::register_mixed_f16(t);
     return t;
   }();
   return m;
@@ -73,10 +49,25 @@ const std::map<std::tuple<int, int, int, int>, Launcher> &launchers() {
 
 // ---- auxiliary kernels ---------------------------------------------------
 
+// Node weight that converts stored values to populations: w_k for the
+// mixed form (phi_k = f_k / w_k), 1 for the FP64 form.
+__device__ __forceinline__ double node_scale(const hhlb::DevTables *tb, int V, int k, int scaled) {
+  return scaled ? tb->w[k % (V / 2)] : 1.0;
+}
+
+// Stored value at index j: the FP64 value, or the mixed form's FP32 value
+// plus its 16-bit correction word.
+__device__ __forceinline__ double stored(const double *y, const int16_t *, int64_t j) { return y[j]; }
+__device__ __forceinline__ double stored(const float *y, const int16_t *lo, int64_t j) {
+  const float hi = y[j];
+  return (double)hi + (double)ldexpf((float)lo[j], __builtin_amdgcn_frexp_expf(hi) - 39);
+}
+
+template <typename S>
 __global__ void moments_kernel(const hhlb::DevTables *tbs, const int32_t *ch_class,
-                               const hhlb::DevChannel *chans, const int32_t *ch_V, int n_ch,
-                               const double *f, const double *c, int has_chi, double *n_out,
-                               double *u_out, double *T_out) {
+                               const hhlb::DevChannel *chans, const int32_t *ch_V, int n_ch, int scaled,
+                               const S *f, const int16_t *flo, const S *c, const int16_t *clo, int has_chi,
+                               double *n_out, double *u_out, double *T_out) {
   const int ch = blockIdx.y;
   if (ch >= n_ch) return;
   const hhlb::DevChannel C = chans[ch];
@@ -85,15 +76,16 @@ __global__ void moments_kernel(const hhlb::DevTables *tbs, const int32_t *ch_cla
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < C.Nx; i += gridDim.x * blockDim.x) {
     double n = 0, mom = 0;
     for (int k = 0; k < V; ++k) {
-      double y = f[C.off + (int64_t)k * C.Nx + i];
+      double y = node_scale(tb, V, k, scaled) * stored(f, flo, C.off + (int64_t)k * C.Nx + i);
       n += y;
       mom += tb->p[k] * y;
     }
     double u = mom / n, e2 = 0, ech = 0;
     for (int k = 0; k < V; ++k) {
+      const double sc = node_scale(tb, V, k, scaled);
       double dp = tb->p[k] - u;
-      e2 += dp * dp * f[C.off + (int64_t)k * C.Nx + i];
-      if (has_chi && C.half_Dt != 0.0) ech += c[C.off + (int64_t)k * C.Nx + i];
+      e2 += dp * dp * sc * stored(f, flo, C.off + (int64_t)k * C.Nx + i);
+      if (has_chi && C.half_Dt != 0.0) ech += sc * stored(c, clo, C.off + (int64_t)k * C.Nx + i);
     }
     n_out[C.cell_off + i] = n;
     u_out[C.cell_off + i] = u;
@@ -101,12 +93,16 @@ __global__ void moments_kernel(const hhlb::DevTables *tbs, const int32_t *ch_cla
   }
 }
 
-__global__ void mass_kernel(const hhlb::DevChannel *chans, const int32_t *ch_V, int n_ch,
-                            const double *f, const double *c, int has_chi, const double *dx,
-                            double *mass, int32_t *nonfinite) {
+// Mass sum_i dx_i n_i per channel (Eq. Ndef) and the count of non-finite
+// stored values (added to nonfinite[0] and flag[0]).
+template <typename S>
+__global__ void mass_kernel(const hhlb::DevTables *tbs, const int32_t *ch_class, const hhlb::DevChannel *chans,
+                            const int32_t *ch_V, int n_ch, int scaled, const S *f, const int16_t *flo, const S *c,
+                            int has_chi, const double *dx, double *mass, int32_t *nonfinite, int32_t *flag) {
   const int ch = blockIdx.x;
   if (ch >= n_ch) return;
   const hhlb::DevChannel C = chans[ch];
+  const hhlb::DevTables *tb = tbs + ch_class[ch];
   const int V = ch_V[ch];
   __shared__ double part[256];
   double acc = 0;
@@ -114,10 +110,11 @@ __global__ void mass_kernel(const hhlb::DevChannel *chans, const int32_t *ch_V, 
   for (int i = threadIdx.x; i < C.Nx; i += blockDim.x) {
     double n = 0;
     for (int k = 0; k < V; ++k) {
-      double y = f[C.off + (int64_t)k * C.Nx + i];
-      n += y;
+      const int64_t j = C.off + (int64_t)k * C.Nx + i;
+      const double y = stored(f, flo, j);
+      n += node_scale(tb, V, k, scaled) * y;
       if (!isfinite(y)) ++bad;
-      if (has_chi && C.half_Dt != 0.0 && !isfinite(c[C.off + (int64_t)k * C.Nx + i])) ++bad;
+      if (has_chi && C.half_Dt != 0.0 && !isfinite((double)c[j])) ++bad;
     }
     acc += dx[C.cell_off + i] * n;
   }
@@ -128,23 +125,102 @@ __global__ void mass_kernel(const hhlb::DevChannel *chans, const int32_t *ch_V, 
     __syncthreads();
   }
   if (threadIdx.x == 0 && mass) mass[ch] = part[0];
-  if (bad && nonfinite) atomicAdd(nonfinite, bad);
+  if (bad) {
+    if (nonfinite) atomicAdd(nonfinite, bad);
+    atomicAdd(flag, bad);
+  }
 }
 
-__global__ void fill_kernel(const hhlb::DevChannel *chans, const int32_t *ch_V, int n_ch,
-                            const double *feq, const int32_t *feq_off, double T0, double *f,
-                            double *c) {
+// Residual per channel: max over f (and chi) of ||y1 - y||_inf / (dt ||y||_inf)
+// with y1 = y + dt L[y] one forward-Euler stage from the current state.
+// d1 holds y1 (FP64 form) or the increment y1 - y (mixed form).
+template <typename S>
+__global__ void residual_kernel(const hhlb::DevTables *tbs, const int32_t *ch_class,
+                                const hhlb::DevChannel *chans, const int32_t *ch_V, int n_ch, int scaled,
+                                int increment, const S *f, const S *f1, const S *c, const S *c1, int has_chi,
+                                double *res) {
+  const int ch = blockIdx.x;
+  if (ch >= n_ch) return;
+  const hhlb::DevChannel C = chans[ch];
+  const hhlb::DevTables *tb = tbs + ch_class[ch];
+  const int V = ch_V[ch];
+  const bool chi = has_chi && C.half_Dt != 0.0;
+  __shared__ double part[4][256];
+  double df = 0, nf = 0, dc = 0, nc = 0;
+  const int64_t total = (int64_t)V * C.Nx;
+  for (int64_t j = threadIdx.x; j < total; j += blockDim.x) {
+    const double sc = node_scale(tb, V, (int)(j / C.Nx), scaled);
+    const double y = (double)f[C.off + j], y1 = (double)f1[C.off + j];
+    df = fmax(df, sc * fabs(increment ? y1 : y1 - y));
+    nf = fmax(nf, sc * fabs(y));
+    if (chi) {
+      const double x = (double)c[C.off + j], x1 = (double)c1[C.off + j];
+      dc = fmax(dc, sc * fabs(increment ? x1 : x1 - x));
+      nc = fmax(nc, sc * fabs(x));
+    }
+  }
+  part[0][threadIdx.x] = df; part[1][threadIdx.x] = nf;
+  part[2][threadIdx.x] = dc; part[3][threadIdx.x] = nc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int q = 0; q < 4; ++q) part[q][threadIdx.x] = fmax(part[q][threadIdx.x], part[q][threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double r = part[0][0] / (C.dt * part[1][0]);
+    if (chi) r = fmax(r, part[2][0] / (C.dt * part[3][0]));
+    res[ch] = r;
+  }
+}
+
+// Store a population value: FP64 as is; mixed form as FP32 value plus the
+// correction word of the rounding error.
+__device__ __forceinline__ void put(double *y, int16_t *, int64_t j, double v) { y[j] = v; }
+__device__ __forceinline__ void put(float *y, int16_t *lo, int64_t j, double v) {
+  const float hi = (float)v;
+  y[j] = hi;
+  const double q = rint(ldexp(v - (double)hi, 39 - __builtin_amdgcn_frexp_expf(hi)));
+  lo[j] = (int16_t)fmin(fmax(q, -32767.0), 32767.0);
+}
+
+// f_k = feq_k in every cell (chi = (Dt/2) T0 f), in the stored form.
+template <typename S>
+__global__ void fill_kernel(const hhlb::DevTables *tbs, const int32_t *ch_class, const hhlb::DevChannel *chans,
+                            const int32_t *ch_V, int n_ch, int scaled, const double *feq, const int32_t *feq_off,
+                            double T0, S *f, int16_t *flo, S *c, int16_t *clo) {
   const int ch = blockIdx.y;
   if (ch >= n_ch) return;
   const hhlb::DevChannel C = chans[ch];
+  const hhlb::DevTables *tb = tbs + ch_class[ch];
   const int V = ch_V[ch];
   const int64_t total = (int64_t)V * C.Nx;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
        j += (int64_t)gridDim.x * blockDim.x) {
     const int k = (int)(j / C.Nx);
-    const double y = feq[feq_off[ch] + k];
-    f[C.off + j] = y;
-    if (c) c[C.off + j] = C.half_Dt * T0 * y;
+    const double y = feq[feq_off[ch] + k] / node_scale(tb, V, k, scaled);
+    put(f, flo, C.off + j, y);
+    if (c) put(c, clo, C.off + j, C.half_Dt * T0 * y);
+  }
+}
+
+// Boundary conversion between FP64 populations and the stored form:
+// to_state: stored = pop / w_k; else pop = w_k * stored.
+template <typename S>
+__global__ void convert_kernel(const hhlb::DevTables *tbs, const int32_t *ch_class, const hhlb::DevChannel *chans,
+                               const int32_t *ch_V, int n_ch, int scaled, int to_state, double *pop, S *st,
+                               int16_t *lo) {
+  const int ch = blockIdx.y;
+  if (ch >= n_ch) return;
+  const hhlb::DevChannel C = chans[ch];
+  const hhlb::DevTables *tb = tbs + ch_class[ch];
+  const int V = ch_V[ch];
+  const int64_t total = (int64_t)V * C.Nx;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const double sc = node_scale(tb, V, (int)(j / C.Nx), scaled);
+    if (to_state) put(st, lo, C.off + j, pop[C.off + j] / sc);
+    else pop[C.off + j] = sc * stored(st, lo, C.off + j);
   }
 }
 
@@ -169,30 +245,56 @@ struct hhlb_solver {
   std::vector<int> ch_class;
   std::vector<ModelClass> classes;
   std::vector<hhlb::DevChannel> dch;
-  std::vector<int64_t> off;     // state offsets (doubles), n_ch+1
+  std::vector<int64_t> off;     // state offsets (elements), n_ch+1
   std::vector<int32_t> cell_off;
   std::vector<double> dx, inv_dx, gw, dts;
   std::vector<int32_t> Vs;
   int64_t total_state = 0, total_cells = 0;
   bool has_chi = false;
+  int precision = HHLB_FP64;
+  size_t esize = sizeof(double);   // bytes per stored population
   hipStream_t stream = nullptr;
   // workspace layout (byte offsets)
   size_t o_tables = 0, o_chans = 0, o_chclass = 0, o_V = 0, o_dx = 0, o_invdx = 0, o_gw = 0,
-         o_nwall = 0, o_feq = 0, o_feqoff = 0, o_state = 0, bytes = 0;
+         o_nwall = 0, o_feq = 0, o_feqoff = 0, o_flag = 0, o_state = 0, bytes = 0;
   char *ws = nullptr;
-  double *fA = nullptr, *fB = nullptr, *fC = nullptr, *cA = nullptr, *cB = nullptr, *cC = nullptr;
+  // stored state.  FP64 form: hi[0] = y^n (the last stage updates it in
+  // place), B and C = RK stage values.  Mixed form: hi[par] + lo[par] = y^n
+  // as FP32 value and 16-bit correction word (a ping-pong pair, par flips
+  // every step), B and C = stage increments y_s - y^n in FP32.
+  void *hiF[2] = {nullptr, nullptr}, *hiC[2] = {nullptr, nullptr};
+  int16_t *loF[2] = {nullptr, nullptr}, *loC[2] = {nullptr, nullptr};
+  void *fB = nullptr, *fC = nullptr, *cB = nullptr, *cC = nullptr;
+  int par = 0;
+  void *fA() const { return hiF[par]; }
+  void *cA() const { return hiC[par]; }
+  int16_t *lA() const { return loF[par]; }
+  int16_t *lcA() const { return loC[par]; }
+  // non-finite count of the last hhlb_diagnostics, read back by the next hhlb_step
+  int32_t *flag_host = nullptr;
+  hipEvent_t ev_flag = nullptr;
+  bool flag_pending = false;
   // graph replay of the step sequence (0 = direct launches)
   int graph_steps = 0;   // direct launches: measured no slower than graph replay
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  hipGraphExec_t gexec_k = nullptr, gexec_1 = nullptr;
+  hipGraphExec_t gexec_k[2] = {nullptr, nullptr}, gexec_1[2] = {nullptr, nullptr};  // per starting parity
+  void drop_graphs() {
+    for (int p = 0; p < 2; ++p) {
+      if (gexec_k[p]) (void)hipGraphExecDestroy(gexec_k[p]);
+      if (gexec_1[p]) (void)hipGraphExecDestroy(gexec_1[p]);
+      gexec_k[p] = gexec_1[p] = nullptr;
+    }
+  }
   ~hhlb_solver() {
-    if (gexec_k) (void)hipGraphExecDestroy(gexec_k);
-    if (gexec_1) (void)hipGraphExecDestroy(gexec_1);
+    drop_graphs();
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (gstream) (void)hipStreamDestroy(gstream);
+    if (ev_flag) (void)hipEventDestroy(ev_flag);
+    if (flag_host) (void)hipHostFree(flag_host);
   }
+  bool mixed() const { return precision != HHLB_FP64; }
 };
 
 namespace {
@@ -232,6 +334,164 @@ void make_grid(const hhlb_channel &c, std::vector<double> &dx) {
     for (int j = 0; j <= Nx; ++j) xf[j] = c.L / (2 * A) * tanhl((j + 0.5L - (Nx + 1) / 2.0L) * deta);
   }
   for (int i = 0; i < Nx; ++i) dx[i] = (double)(xf[i + 1] - xf[i]);
+}
+
+// Round-to-nearest-even conversions of FP32 values, as the matrix-core
+// operands see them (finite values of normal range).
+float round_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  u &= 0xFFFF0000u;
+  float y;
+  std::memcpy(&y, &u, 4);
+  return y;
+}
+float round_f16(float x) { return (float)(_Float16)x; }
+
+// Device tables of one model class (quadrature, Q, N, p0).
+hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb::Rule &r, hhlb::DevTables &d) {
+  std::memset(&d, 0, sizeof(d));
+  for (int k = 0; k < r.V; ++k) d.p[k] = r.p[k];
+  for (int k = 0; k < r.H; ++k) { d.z[k] = (double)r.z[k]; d.w[k] = (double)r.w[k]; }
+  for (int l = 0; l < h.Q + 1 && l < (int)r.a.size(); ++l) d.a[l] = (double)r.a[l];
+  for (int l = 0; l < h.Q + 2 && l < (int)r.b.size(); ++l) {
+    d.sb[l] = (double)sqrtl(r.b[l]);
+    d.isb[l] = (double)(1.0L / sqrtl(r.b[l]));
+  }
+  if (h.quad == HHLB_HALF_HERMITE) {
+    for (int j = 0; j < r.H * r.H; ++j) d.Kin[j] = r.Kin[j];
+    for (int k = 0; k < r.H; ++k) { d.ka[k] = r.ka[k]; d.kb[k] = r.kb[k]; }
+    for (int k = 0; k < r.H; ++k)
+      for (int l = 0; l < h.Q; ++l) d.HW[k * h.Q + l] = l <= N ? r.HW[(size_t)k * h.Q + l] : 0.0;
+  } else {
+    for (int j = 0; j < r.V * r.V; ++j) d.Kin[j] = r.K[j];
+    for (int k = 0; k < r.V; ++k)
+      for (int l = 0; l < h.Q; ++l) d.HW[k * h.Q + l] = l <= N ? r.HW[(size_t)k * h.Q + l] : 0.0;
+  }
+  std::vector<long double> tau, lam;
+  hhlb::gauss_legendre01(hhlb::kNc, tau, lam);
+  const long double inv_s2pi = 1.0L / sqrtl(2 * 3.141592653589793238462643383279502884L);
+  for (int j = 0; j < hhlb::kNc; ++j) { d.tau[j] = (double)tau[j]; d.lamw[j] = (double)(lam[j] * inv_s2pi); }
+  d.inv_p0 = 1.0 / h.p0;
+  // monic recurrence and the normalisation folded into the contraction
+  std::vector<long double> HWs((size_t)r.H * h.Q, 0.0L);
+  {
+    long double prod = 1;
+    for (int l = 0; l < h.Q + 1 && l < (int)r.b.size(); ++l) d.mb[l] = (double)r.b[l];
+    std::vector<long double> inv_norm(h.Q);
+    for (int l = 0; l < h.Q; ++l) { prod *= r.b[l]; inv_norm[l] = 1.0L / sqrtl(prod); }
+    if (h.quad == HHLB_HALF_HERMITE)
+      for (int k = 0; k < r.H; ++k)
+        for (int l = 0; l < h.Q; ++l) {
+          HWs[(size_t)k * h.Q + l] = l <= N ? (long double)r.HW[(size_t)k * h.Q + l] * inv_norm[l] : 0.0L;
+          d.HWs[k * h.Q + l] = (double)HWs[(size_t)k * h.Q + l];
+        }
+  }
+  if (h.quad == HHLB_HALF_HERMITE) {
+    // main rule of the half-range equilibrium: M = ceil((N+1)/2) points
+    const int M = (N + 2) / 2;
+    hhlb::Rule rm;
+    std::string err2;
+    int st2 = hhlb::build_rule(HHLB_HALF_HERMITE, M, 1.0, rm, err2);
+    if (st2) return fail(st2, "equilibrium rule: " + err2);
+    d.nm = M;
+    for (int j = 0; j < M; ++j) { d.zm[j] = (double)rm.z[j]; d.wm[j] = (double)rm.w[j]; }
+    // tables of the scaled (phi = f / w) mixed-precision form
+    for (int k = 0; k < r.H; ++k) {
+      const long double wk = r.w[k];
+      d.wq[k] = (double)wk;
+      d.iwq[k] = (double)(1.0L / wk);
+      d.kbs[k] = (double)((long double)r.kb[k] * wk);
+      d.kas[k] = (float)((long double)r.ka[k] / wk);
+      for (int j = 0; j < r.H; ++j) d.Ks[k * r.H + j] = (float)((long double)r.Kin[k * r.H + j] * r.w[j] / wk);
+      for (int l = 0; l < h.Q; ++l) d.HWss[k * h.Q + l] = (double)(HWs[(size_t)k * h.Q + l] / wk);
+    }
+    for (int k = 0; k < r.V; ++k) {
+      const long double wk = r.w[k % r.H], pk = r.p[k];
+      d.wpq[k] = (double)(wk * pk);
+      d.wpfq[k] = (double)(wk * (long double)(float)r.p[k]);
+      d.wp2q[k] = (double)(wk * pk * pk);
+      d.pf[k] = (float)r.p[k];
+    }
+    // reduced-precision operands: FP16 row scales, and the weighted column
+    // sums of the block exactly as the matrix cores round it
+    long double wsum = 0;
+    for (int k = 0; k < r.H; ++k) wsum += r.w[k];
+    d.iwh = (float)(1.0L / wsum);
+    for (int k = 0; k < r.H; ++k) {
+      float m = 0.0f;
+      for (int j = 0; j < r.H; ++j) m = std::max(m, std::fabs(d.Ks[k * r.H + j]));
+      int e = 0;
+      std::frexp(m, &e);
+      const float rs = std::ldexp(1.0f, -e);
+      d.irsc[k] = std::ldexp(1.0f, e);
+      for (int j = 0; j < r.H; ++j) d.Ks16[k * r.H + j] = d.Ks[k * r.H + j] * rs;
+    }
+    for (int j = 0; j < r.H; ++j) {
+      long double c = 0;
+      for (int k = 0; k < r.H; ++k) {
+        float kr = d.Ks[k * r.H + j];
+        if (precision == HHLB_MIXED_BF16) kr = round_bf16(kr);
+        else if (precision == HHLB_MIXED_F16) kr = round_f16(d.Ks16[k * r.H + j]) * d.irsc[k];
+        c += r.w[k] * (long double)kr;
+      }
+      d.crs[j] = (float)c;
+    }
+  }
+  // correction ladder (half range): point counts and the |y0| each covers
+  const int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
+  int o = 0;
+  for (int j = 0; j < hhlb::kLadder; ++j) {
+    d.lad_n[j] = counts[j];
+    d.lad_off[j] = o;
+    d.lad_y[j] = h.quad == HHLB_HALF_HERMITE ? hhlb::correction_limit(r, N, counts[j], 3e-16) : 0.0;
+    if (counts[j] > 0) {
+      std::vector<long double> t2, l2;
+      hhlb::gauss_legendre01(counts[j], t2, l2);
+      for (int q = 0; q < counts[j]; ++q) {
+        d.ltau[o + q] = (double)t2[q];
+        d.llamw[o + q] = (double)(l2[q] * inv_s2pi);
+      }
+    }
+    o += counts[j];
+  }
+  return HHLB_OK;
+}
+
+// Kernel launch arguments shared by the aux kernels.
+struct AuxArgs {
+  const hhlb::DevTables *tbs;
+  const int32_t *ch_class;
+  const hhlb::DevChannel *chans;
+  const int32_t *ch_V;
+  int n_ch, scaled;
+};
+
+AuxArgs aux(const hhlb_solver *s) {
+  return AuxArgs{(const hhlb::DevTables *)(s->ws + s->o_tables), (const int32_t *)(s->ws + s->o_chclass),
+                 (const hhlb::DevChannel *)(s->ws + s->o_chans), (const int32_t *)(s->ws + s->o_V),
+                 (int)s->ch.size(), s->mixed() ? 1 : 0};
+}
+
+dim3 state_grid(const hhlb_solver *s) {
+  int64_t maxlen = 0;
+  for (size_t c = 0; c + 1 < s->off.size(); ++c) maxlen = std::max<int64_t>(maxlen, s->off[c + 1] - s->off[c]);
+  return dim3((unsigned)std::min<int64_t>((maxlen + 255) / 256, 4096), (unsigned)s->ch.size());
+}
+
+template <typename S>
+void launch_convert(const hhlb_solver *s, int to_state, double *pop, void *st, int16_t *lo) {
+  const AuxArgs a = aux(s);
+  hipLaunchKernelGGL(convert_kernel<S>, state_grid(s), dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans, a.ch_V,
+                     a.n_ch, a.scaled, to_state, pop, (S *)st, lo);
+}
+
+// pop (FP64, boundary layout) <-> stored state of function fn (0 = f, 1 = chi)
+void convert(const hhlb_solver *s, int to_state, double *pop, int fn) {
+  void *st = fn == 0 ? s->fA() : s->cA();
+  if (s->mixed()) launch_convert<float>(s, to_state, pop, st, fn == 0 ? s->lA() : s->lcA());
+  else launch_convert<double>(s, to_state, pop, st, nullptr);
 }
 
 }  // namespace
@@ -290,15 +550,20 @@ hhlb_status hhlb_equilibrium(int32_t quad, int32_t Q, int32_t N, double p0, doub
 hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t precision,
                         void *hip_stream, hhlb_solver **out) {
   if (!channels || !out || n_ch < 1) return fail(HHLB_E_ARG, "need channels, n_ch >= 1 and out");
-  if (precision != HHLB_FP64) return fail(HHLB_E_UNSUPPORTED, "only HHLB_FP64 is available");
+  if (precision < HHLB_FP64 || precision > HHLB_MIXED_F16) return fail(HHLB_E_ARG, "unknown precision");
   for (int c = 0; c < n_ch; ++c) {
     hhlb_status st = check_channel(channels[c], c);
     if (st) return st;
+    if (precision != HHLB_FP64 && channels[c].quad != HHLB_HALF_HERMITE)
+      return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) +
+                                          ": the mixed-precision forms cover the half-range model only");
   }
   std::unique_ptr<hhlb_solver> s;
   try {
     s.reset(new hhlb_solver());
     s->stream = (hipStream_t)hip_stream;
+    s->precision = precision;
+    s->esize = precision == HHLB_FP64 ? sizeof(double) : sizeof(float);
     s->ch.assign(channels, channels + n_ch);
     std::map<std::tuple<int, int, int, int, int, double>, int> cls;
     s->off.assign(n_ch + 1, 0);
@@ -315,77 +580,13 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
         std::string err;
         int st = hhlb::build_rule(h.quad, h.Q, h.p0, mc.rule, err);
         if (st) return fail(st, "channel " + std::to_string(c) + ": " + err);
-        auto lk = launchers().find({h.quad, h.Q, h.transverse_dof > 0 ? 2 : 1, h.adv});
+        auto lk = launchers().find({h.quad, h.Q, h.transverse_dof > 0 ? 2 : 1, h.adv, precision});
         if (lk == launchers().end())
           return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) + ": no kernel for quad=" +
                                               std::to_string(h.quad) + " Q=" + std::to_string(h.Q));
         mc.launch = lk->second;
-        // device tables
-        hhlb::DevTables &d = mc.dev;
-        std::memset(&d, 0, sizeof(d));
-        const hhlb::Rule &r = mc.rule;
-        for (int k = 0; k < r.V; ++k) d.p[k] = r.p[k];
-        for (int k = 0; k < r.H; ++k) { d.z[k] = (double)r.z[k]; d.w[k] = (double)r.w[k]; }
-        for (int l = 0; l < h.Q + 1 && l < (int)r.a.size(); ++l) d.a[l] = (double)r.a[l];
-        for (int l = 0; l < h.Q + 2 && l < (int)r.b.size(); ++l) {
-          d.sb[l] = (double)sqrtl(r.b[l]);
-          d.isb[l] = (double)(1.0L / sqrtl(r.b[l]));
-        }
-        if (h.quad == HHLB_HALF_HERMITE) {
-          for (int j = 0; j < r.H * r.H; ++j) d.Kin[j] = r.Kin[j];
-          for (int k = 0; k < r.H; ++k) { d.ka[k] = r.ka[k]; d.kb[k] = r.kb[k]; }
-          for (int k = 0; k < r.H; ++k)
-            for (int l = 0; l < h.Q; ++l) d.HW[k * h.Q + l] = l <= N ? r.HW[(size_t)k * h.Q + l] : 0.0;
-        } else {
-          for (int j = 0; j < r.V * r.V; ++j) d.Kin[j] = r.K[j];
-          for (int k = 0; k < r.V; ++k)
-            for (int l = 0; l < h.Q; ++l) d.HW[k * h.Q + l] = l <= N ? r.HW[(size_t)k * h.Q + l] : 0.0;
-        }
-        std::vector<long double> tau, lam;
-        hhlb::gauss_legendre01(hhlb::kNc, tau, lam);
-        const long double inv_s2pi = 1.0L / sqrtl(2 * 3.141592653589793238462643383279502884L);
-        for (int j = 0; j < hhlb::kNc; ++j) { d.tau[j] = (double)tau[j]; d.lamw[j] = (double)(lam[j] * inv_s2pi); }
-        d.inv_p0 = 1.0 / h.p0;
-        // monic recurrence and the normalisation folded into the contraction
-        {
-          long double prod = 1;
-          for (int l = 0; l < h.Q + 1 && l < (int)r.b.size(); ++l) d.mb[l] = (double)r.b[l];
-          std::vector<long double> inv_norm(h.Q);
-          for (int l = 0; l < h.Q; ++l) { prod *= r.b[l]; inv_norm[l] = 1.0L / sqrtl(prod); }
-          if (h.quad == HHLB_HALF_HERMITE)
-            for (int k = 0; k < r.H; ++k)
-              for (int l = 0; l < h.Q; ++l)
-                d.HWs[k * h.Q + l] = l <= N ? (double)((long double)r.HW[(size_t)k * h.Q + l] * inv_norm[l]) : 0.0;
-        }
-        // main rule of the half-range equilibrium: M = ceil((N+1)/2) points
-        if (h.quad == HHLB_HALF_HERMITE) {
-          const int M = (N + 2) / 2;
-          hhlb::Rule rm;
-          std::string err2;
-          int st2 = hhlb::build_rule(HHLB_HALF_HERMITE, M, 1.0, rm, err2);
-          if (st2) return fail(st2, "equilibrium rule: " + err2);
-          d.nm = M;
-          for (int j = 0; j < M; ++j) { d.zm[j] = (double)rm.z[j]; d.wm[j] = (double)rm.w[j]; }
-        }
-        // correction ladder (half range): point counts and the |y0| each covers
-        {
-          const int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
-          int o = 0;
-          for (int j = 0; j < hhlb::kLadder; ++j) {
-            d.lad_n[j] = counts[j];
-            d.lad_off[j] = o;
-            d.lad_y[j] = h.quad == HHLB_HALF_HERMITE ? hhlb::correction_limit(r, N, counts[j], 3e-16) : 0.0;
-            if (counts[j] > 0) {
-              std::vector<long double> t2, l2;
-              hhlb::gauss_legendre01(counts[j], t2, l2);
-              for (int q = 0; q < counts[j]; ++q) {
-                d.ltau[o + q] = (double)t2[q];
-                d.llamw[o + q] = (double)(l2[q] * inv_s2pi);
-              }
-            }
-            o += counts[j];
-          }
-        }
+        st = make_tables(h, N, precision, mc.rule, mc.dev);
+        if (st) return st;
         id = (int)s->classes.size();
         s->classes.push_back(std::move(mc));
         cls[key] = id;
@@ -426,8 +627,11 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
       hhlb::equilibrium(r, mc.N, 0.0L, (long double)h.T_right, gR.data());
       long double DL = 0, DR = 0;
       for (int k = 0; k < r.V; ++k) {
-        if (k < r.H) DL += (long double)r.p[k] * gL[k];
-        else DR += (long double)r.p[k] * gR[k];
+        // the mixed form's FP32 advection moves the emergent populations with
+        // the FP32-rounded velocities
+        const long double pk = s->mixed() ? (long double)(float)r.p[k] : (long double)r.p[k];
+        if (k < r.H) DL += pk * gL[k];
+        else DR += pk * gR[k];
       }
       hhlb::DevChannel d;
       std::memset(&d, 0, sizeof(d));
@@ -465,9 +669,14 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
     for (int c = 0; c < n_ch; ++c) feq_total += s->Vs[c];
     s->o_feq = take(sizeof(double) * feq_total);
     s->o_feqoff = take(sizeof(int32_t) * n_ch);
+    s->o_flag = take(sizeof(int32_t));
     s->o_state = o;
-    const int ncopies = s->has_chi ? 6 : 3;
-    for (int j = 0; j < ncopies; ++j) take(sizeof(double) * s->total_state);
+    // per function: FP64 form 3 copies of 8 bytes; mixed form 4 copies of
+    // 4 bytes (hi x 2, B, C) and 2 copies of 2 bytes (lo x 2)
+    const int nfun = s->has_chi ? 2 : 1;
+    for (int j = 0; j < nfun * (s->mixed() ? 4 : 3); ++j) take(s->esize * s->total_state);
+    if (s->mixed())
+      for (int j = 0; j < nfun * 2; ++j) take(sizeof(int16_t) * s->total_state);
     s->bytes = o;
   } catch (...) {
     return fail(HHLB_E_NOMEM, "host allocation failed");
@@ -513,14 +722,29 @@ hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr) {
   HIP_TRY(hipMemcpyAsync(ws + s->o_feqoff, feq_off.data(), sizeof(int32_t) * n_ch,
                          hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemsetAsync(ws + s->o_nwall, 0, sizeof(double) * 2 * n_ch, s->stream));
+  HIP_TRY(hipMemsetAsync(ws + s->o_flag, 0, sizeof(int32_t), s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->ws = ws;
-  if (s->gexec_k) { (void)hipGraphExecDestroy(s->gexec_k); s->gexec_k = nullptr; }
-  if (s->gexec_1) { (void)hipGraphExecDestroy(s->gexec_1); s->gexec_1 = nullptr; }
-  double *st = (double *)(ws + s->o_state);
-  const size_t stride = align256(sizeof(double) * s->total_state) / sizeof(double);
-  s->fA = st; s->fB = st + stride; s->fC = st + 2 * stride;
-  if (s->has_chi) { s->cA = st + 3 * stride; s->cB = st + 4 * stride; s->cC = st + 5 * stride; }
+  s->flag_pending = false;
+  s->drop_graphs();
+  s->par = 0;
+  char *st = ws + s->o_state;
+  const size_t stride = align256(s->esize * s->total_state);
+  auto next = [&](size_t bytes) { char *p = st; st += align256(bytes); return (void *)p; };
+  const size_t vb = s->esize * s->total_state, lb = sizeof(int16_t) * s->total_state;
+  s->hiF[0] = next(vb); s->fB = next(vb); s->fC = next(vb);
+  s->hiF[1] = s->mixed() ? next(vb) : nullptr;
+  if (s->has_chi) {
+    s->hiC[0] = next(vb); s->cB = next(vb); s->cC = next(vb);
+    s->hiC[1] = s->mixed() ? next(vb) : nullptr;
+  } else {
+    s->hiC[0] = s->hiC[1] = s->cB = s->cC = nullptr;
+  }
+  if (s->mixed()) {
+    s->loF[0] = (int16_t *)next(lb); s->loF[1] = (int16_t *)next(lb);
+    if (s->has_chi) { s->loC[0] = (int16_t *)next(lb); s->loC[1] = (int16_t *)next(lb); }
+  }
+  (void)stride;
   return HHLB_OK;
 }
 
@@ -540,22 +764,31 @@ hhlb_status hhlb_set_state(hhlb_solver *s, const double *f_dev, const double *ch
   if (!s || !f_dev) return fail(HHLB_E_ARG, "null argument");
   if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
   if (s->has_chi && !chi_dev) return fail(HHLB_E_ARG, "chi is required when a channel has Dt > 0");
-  HIP_TRY(hipMemcpyAsync(s->fA, f_dev, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
-  if (s->has_chi)
-    HIP_TRY(hipMemcpyAsync(s->cA, chi_dev, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
+  if (!s->mixed()) {
+    HIP_TRY(hipMemcpyAsync(s->fA(), f_dev, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
+    if (s->has_chi)
+      HIP_TRY(hipMemcpyAsync(s->cA(), chi_dev, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
+  } else {
+    convert(s, 1, const_cast<double *>(f_dev), 0);
+    if (s->has_chi) convert(s, 1, const_cast<double *>(chi_dev), 1);
+    HIP_TRY(hipGetLastError());
+  }
   return HHLB_OK;
 }
 
 hhlb_status hhlb_get_state(const hhlb_solver *s, double *f_dev, double *chi_dev) {
   if (!s || !f_dev) return fail(HHLB_E_ARG, "null argument");
   if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
-  HIP_TRY(hipMemcpyAsync(f_dev, s->fA, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
-  if (chi_dev) {
-    if (s->has_chi)
-      HIP_TRY(hipMemcpyAsync(chi_dev, s->cA, sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
-    else
-      HIP_TRY(hipMemsetAsync(chi_dev, 0, sizeof(double) * s->total_state, s->stream));
+  if (!s->mixed()) {
+    HIP_TRY(hipMemcpyAsync(f_dev, s->fA(), sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
+    if (chi_dev && s->has_chi)
+      HIP_TRY(hipMemcpyAsync(chi_dev, s->cA(), sizeof(double) * s->total_state, hipMemcpyDeviceToDevice, s->stream));
+  } else {
+    convert(s, 0, f_dev, 0);
+    if (chi_dev && s->has_chi) convert(s, 0, chi_dev, 1);
+    HIP_TRY(hipGetLastError());
   }
+  if (chi_dev && !s->has_chi) HIP_TRY(hipMemsetAsync(chi_dev, 0, sizeof(double) * s->total_state, s->stream));
   return HHLB_OK;
 }
 
@@ -574,13 +807,17 @@ hhlb_status hhlb_init_equilibrium(hhlb_solver *s, double n0, double u0, double T
   HIP_TRY(hipMemcpyAsync(s->ws + s->o_feq, feq.data(), sizeof(double) * feq.size(), hipMemcpyHostToDevice,
                          s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  int64_t maxlen = 0;
-  for (int c = 0; c < n_ch; ++c) maxlen = std::max<int64_t>(maxlen, s->off[c + 1] - s->off[c]);
-  dim3 grid((unsigned)std::min<int64_t>((maxlen + 255) / 256, 4096), n_ch);
-  hipLaunchKernelGGL(fill_kernel, grid, dim3(256), 0, s->stream,
-                     (const hhlb::DevChannel *)(s->ws + s->o_chans), (const int32_t *)(s->ws + s->o_V), n_ch,
-                     (const double *)(s->ws + s->o_feq), (const int32_t *)(s->ws + s->o_feqoff), T0, s->fA,
-                     s->has_chi ? s->cA : nullptr);
+  const AuxArgs a = aux(s);
+  const double *fq = (const double *)(s->ws + s->o_feq);
+  const int32_t *fo = (const int32_t *)(s->ws + s->o_feqoff);
+  if (s->mixed())
+    hipLaunchKernelGGL(fill_kernel<float>, state_grid(s), dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans,
+                       a.ch_V, a.n_ch, a.scaled, fq, fo, T0, (float *)s->fA(), s->lA(), (float *)s->cA(),
+                       s->lcA());
+  else
+    hipLaunchKernelGGL(fill_kernel<double>, state_grid(s), dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans,
+                       a.ch_V, a.n_ch, a.scaled, fq, fo, T0, (double *)s->fA(), (int16_t *)nullptr,
+                       (double *)s->cA(), (int16_t *)nullptr);
   HIP_TRY(hipGetLastError());
   return HHLB_OK;
 }
@@ -589,42 +826,62 @@ hhlb_status hhlb_init_equilibrium(hhlb_solver *s, double n0, double u0, double T
 
 namespace {
 
-// Enqueue n_steps RK-3 steps (three stage launches per model class each).
+// Enqueue one RK stage for every model class.
+void enqueue_stage(hhlb_solver *s, int stage, const void *inf, const void *inc, void *outf, void *outc,
+                   double a_base, double b_stage, hipStream_t stream, const int16_t *lo_in_f = nullptr,
+                   const int16_t *lo_in_c = nullptr, int16_t *lo_out_f = nullptr, int16_t *lo_out_c = nullptr) {
+  for (size_t ci = 0; ci < s->classes.size(); ++ci) {
+    ModelClass &mc = s->classes[ci];
+    hhlb::StageArgs a;
+    a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables) + ci;
+    a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
+    a.wins = (const hhlb::DevWindow *)(s->ws + mc.win_off);
+    a.nwin = (int32_t)mc.windows.size();
+    a.stage = stage;
+    a.inv_dx = (const double *)(s->ws + s->o_invdx);
+    a.gw = (const double *)(s->ws + s->o_gw);
+    a.in_f = inf; a.in_c = inc;
+    a.base_f = s->fA(); a.base_c = s->cA();
+    a.out_f = outf; a.out_c = outc;
+    a.a_base = a_base;
+    a.b_stage = b_stage;
+    a.nwall = (double *)(s->ws + s->o_nwall);
+    a.lo_in_f = lo_in_f; a.lo_in_c = lo_in_c;
+    a.lo_out_f = lo_out_f; a.lo_out_c = lo_out_c;
+    mc.launch(a, stream);
+  }
+}
+
+// Enqueue n_steps RK-3 steps (Eq. rk3).
+//  FP64: stage 1 A -> B, stage 2 B -> C, stage 3 C -> A (pointwise in y^n,
+//        so in place is safe).
+//  Mixed: stage 1 hi -> d1 (B), stage 2 (hi, d1) -> d2 (C), stage 3
+//        (hi, lo, d2) -> the other (hi, lo) copy; the parity then flips.
 void enqueue_steps(hhlb_solver *s, int64_t n_steps, hipStream_t stream) {
-  const double ab[3] = {0.0, 0.75, 1.0 / 3.0};
-  const double bs[3] = {1.0, 0.25, 2.0 / 3.0};
   for (int64_t step = 0; step < n_steps; ++step) {
-    for (int stage = 0; stage < 3; ++stage) {
-      const double *inf = stage == 0 ? s->fA : (stage == 1 ? s->fB : s->fC);
-      const double *inc = stage == 0 ? s->cA : (stage == 1 ? s->cB : s->cC);
-      double *outf = stage == 0 ? s->fB : (stage == 1 ? s->fC : s->fA);
-      double *outc = stage == 0 ? s->cB : (stage == 1 ? s->cC : s->cA);
-      for (size_t ci = 0; ci < s->classes.size(); ++ci) {
-        ModelClass &mc = s->classes[ci];
-        hhlb::StageArgs a;
-        a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables) + ci;
-        a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
-        a.wins = (const hhlb::DevWindow *)(s->ws + mc.win_off);
-        a.nwin = (int32_t)mc.windows.size();
-        a.stage = stage;
-        a.inv_dx = (const double *)(s->ws + s->o_invdx);
-        a.gw = (const double *)(s->ws + s->o_gw);
-        a.in_f = inf; a.in_c = inc;
-        a.base_f = s->fA; a.base_c = s->cA;
-        a.out_f = outf; a.out_c = outc;
-        a.a_base = ab[stage];
-        a.b_stage = bs[stage];
-        a.nwall = (double *)(s->ws + s->o_nwall);
-        mc.launch(a, stream);
-      }
+    if (!s->mixed()) {
+      enqueue_stage(s, 0, s->fA(), s->cA(), s->fB, s->cB, 0.0, 1.0, stream);
+      enqueue_stage(s, 1, s->fB, s->cB, s->fC, s->cC, 0.75, 0.25, stream);
+      enqueue_stage(s, 2, s->fC, s->cC, s->fA(), s->cA(), 1.0 / 3.0, 2.0 / 3.0, stream);
+    } else {
+      const int p = s->par, q = p ^ 1;
+      enqueue_stage(s, 0, nullptr, nullptr, s->fB, s->cB, 0.0, 1.0, stream);
+      enqueue_stage(s, 1, s->fB, s->cB, s->fC, s->cC, 0.75, 0.25, stream);
+      enqueue_stage(s, 2, s->fC, s->cC, s->hiF[q], s->hiC[q], 1.0 / 3.0, 2.0 / 3.0, stream, s->loF[p], s->loC[p],
+                    s->loF[q], s->loC[q]);
+      s->par = q;
     }
   }
 }
 
+// Capture `steps` steps starting from the current parity (the parity the
+// capture advanced is restored: nothing ran yet).
 hhlb_status make_graph(hhlb_solver *s, int64_t steps, hipGraphExec_t *out) {
   hipGraph_t g = nullptr;
+  const int par0 = s->par;
   HIP_TRY(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal));
   enqueue_steps(s, steps, s->gstream);
+  s->par = par0;
   hipError_t e = hipStreamEndCapture(s->gstream, &g);
   if (e != hipSuccess) return fail(HHLB_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -639,6 +896,13 @@ extern "C" hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
   if (!s) return fail(HHLB_E_ARG, "null solver");
   if (n_steps < 0) return fail(HHLB_E_ARG, "n_steps must be >= 0");
   if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  if (s->flag_pending) {
+    // the non-finite count of the last hhlb_diagnostics
+    HIP_TRY(hipEventSynchronize(s->ev_flag));
+    s->flag_pending = false;
+    if (*s->flag_host > 0)
+      return fail(HHLB_E_NUMERIC, std::to_string(*s->flag_host) + " non-finite populations in the state");
+  }
   if (n_steps == 0) return HHLB_OK;
   if (s->graph_steps <= 0) {
     enqueue_steps(s, n_steps, s->stream);
@@ -652,17 +916,33 @@ extern "C" hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
     HIP_TRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
   }
-  if (!s->gexec_k) {
-    hhlb_status st = make_graph(s, s->graph_steps, &s->gexec_k);
-    if (st) return st;
-    st = make_graph(s, 1, &s->gexec_1);
-    if (st) return st;
-  }
   HIP_TRY(hipEventRecord(s->ev_in, s->stream));
   HIP_TRY(hipStreamWaitEvent(s->gstream, s->ev_in, 0));
   const int64_t full = n_steps / s->graph_steps, rest = n_steps % s->graph_steps;
-  for (int64_t r = 0; r < full; ++r) HIP_TRY(hipGraphLaunch(s->gexec_k, s->gstream));
-  for (int64_t r = 0; r < rest; ++r) HIP_TRY(hipGraphLaunch(s->gexec_1, s->gstream));
+  // the mixed form flips the state parity every step: one graph per
+  // starting parity, all captured before the first launch
+  for (int p = 0; p < (s->mixed() ? 2 : 1); ++p) {
+    const int par0 = s->par;
+    s->par = p;
+    hhlb_status st = HHLB_OK;
+    if (full && !s->gexec_k[p]) st = make_graph(s, s->graph_steps, &s->gexec_k[p]);
+    if (!st && rest && !s->gexec_1[p]) st = make_graph(s, 1, &s->gexec_1[p]);
+    s->par = par0;
+    if (st) return st;
+  }
+  auto launch = [&](int64_t k, hipGraphExec_t *ex) -> hhlb_status {
+    HIP_TRY(hipGraphLaunch(ex[s->par], s->gstream));
+    if (s->mixed() && (k & 1)) s->par ^= 1;
+    return HHLB_OK;
+  };
+  for (int64_t r = 0; r < full; ++r) {
+    hhlb_status st = launch(s->graph_steps, s->gexec_k);
+    if (st) return st;
+  }
+  for (int64_t r = 0; r < rest; ++r) {
+    hhlb_status st = launch(1, s->gexec_1);
+    if (st) return st;
+  }
   HIP_TRY(hipEventRecord(s->ev_out, s->gstream));
   HIP_TRY(hipStreamWaitEvent(s->stream, s->ev_out, 0));
   return HHLB_OK;
@@ -670,8 +950,7 @@ extern "C" hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
 
 extern "C" hhlb_status hhlb_set_graph_steps(hhlb_solver *s, int32_t steps_per_graph) {
   if (!s || steps_per_graph < 0) return fail(HHLB_E_ARG, "need a solver and steps_per_graph >= 0");
-  if (s->gexec_k) { (void)hipGraphExecDestroy(s->gexec_k); s->gexec_k = nullptr; }
-  if (s->gexec_1) { (void)hipGraphExecDestroy(s->gexec_1); s->gexec_1 = nullptr; }
+  s->drop_graphs();
   s->graph_steps = steps_per_graph;
   return HHLB_OK;
 }
@@ -681,34 +960,71 @@ extern "C" {
 hhlb_status hhlb_moments(const hhlb_solver *s, double *n_dev, double *u_dev, double *T_dev) {
   if (!s || !n_dev || !u_dev || !T_dev) return fail(HHLB_E_ARG, "null argument");
   if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
-  const int n_ch = (int)s->ch.size();
   int maxNx = 0;
   for (auto &c : s->ch) maxNx = std::max(maxNx, c.Nx);
-  dim3 grid((maxNx + 255) / 256, n_ch);
-  hipLaunchKernelGGL(moments_kernel, grid, dim3(256), 0, s->stream,
-                     (const hhlb::DevTables *)(s->ws + s->o_tables), (const int32_t *)(s->ws + s->o_chclass),
-                     (const hhlb::DevChannel *)(s->ws + s->o_chans), (const int32_t *)(s->ws + s->o_V), n_ch,
-                     s->fA, s->cA, s->has_chi ? 1 : 0, n_dev, u_dev, T_dev);
+  dim3 grid((maxNx + 255) / 256, (unsigned)s->ch.size());
+  const AuxArgs a = aux(s);
+  const int hc = s->has_chi ? 1 : 0;
+  if (s->mixed())
+    hipLaunchKernelGGL(moments_kernel<float>, grid, dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans, a.ch_V,
+                       a.n_ch, a.scaled, (const float *)s->fA(), (const int16_t *)s->lA(), (const float *)s->cA(),
+                       (const int16_t *)s->lcA(), hc, n_dev, u_dev, T_dev);
+  else
+    hipLaunchKernelGGL(moments_kernel<double>, grid, dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans, a.ch_V,
+                       a.n_ch, a.scaled, (const double *)s->fA(), (const int16_t *)nullptr, (const double *)s->cA(),
+                       (const int16_t *)nullptr, hc, n_dev, u_dev, T_dev);
   HIP_TRY(hipGetLastError());
   return HHLB_OK;
 }
 
-hhlb_status hhlb_diagnostics(const hhlb_solver *s, double *n_wall_dev, double *mass_dev,
+hhlb_status hhlb_diagnostics(hhlb_solver *s, double *n_wall_dev, double *mass_dev, double *residual_dev,
                              int32_t *nonfinite_dev) {
   if (!s) return fail(HHLB_E_ARG, "null solver");
   if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
   const int n_ch = (int)s->ch.size();
+  const AuxArgs a = aux(s);
+  const int hc = s->has_chi ? 1 : 0;
   if (n_wall_dev)
     HIP_TRY(hipMemcpyAsync(n_wall_dev, s->ws + s->o_nwall, sizeof(double) * 2 * n_ch, hipMemcpyDeviceToDevice,
                            s->stream));
-  if (mass_dev || nonfinite_dev) {
-    if (nonfinite_dev) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, s->stream, nonfinite_dev);
-    hipLaunchKernelGGL(mass_kernel, dim3(n_ch), dim3(256), 0, s->stream,
-                       (const hhlb::DevChannel *)(s->ws + s->o_chans), (const int32_t *)(s->ws + s->o_V), n_ch,
-                       s->fA, s->cA, s->has_chi ? 1 : 0, (const double *)(s->ws + s->o_dx), mass_dev,
-                       nonfinite_dev);
+  if (residual_dev) {
+    // one forward-Euler stage from the current state into the B copies; the
+    // state (A) and the wall densities are left untouched
+    if (s->mixed()) {
+      enqueue_stage(s, 0, nullptr, nullptr, s->fB, s->cB, 0.0, 1.0, s->stream);
+      hipLaunchKernelGGL(residual_kernel<float>, dim3(n_ch), dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans,
+                         a.ch_V, a.n_ch, a.scaled, 1, (const float *)s->fA(), (const float *)s->fB,
+                         (const float *)s->cA(), (const float *)s->cB, hc, residual_dev);
+    } else {
+      enqueue_stage(s, 0, s->fA(), s->cA(), s->fB, s->cB, 0.0, 1.0, s->stream);
+      hipLaunchKernelGGL(residual_kernel<double>, dim3(n_ch), dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans,
+                         a.ch_V, a.n_ch, a.scaled, 0, (const double *)s->fA(), (const double *)s->fB,
+                         (const double *)s->cA(), (const double *)s->cB, hc, residual_dev);
+    }
     HIP_TRY(hipGetLastError());
   }
+  // mass and the non-finite count (always taken: hhlb_step reports it)
+  if (!s->flag_host) {
+    HIP_TRY(hipHostMalloc((void **)&s->flag_host, sizeof(int32_t), hipHostMallocDefault));
+    *s->flag_host = 0;
+    HIP_TRY(hipEventCreateWithFlags(&s->ev_flag, hipEventDisableTiming));
+  }
+  int32_t *flag = (int32_t *)(s->ws + s->o_flag);
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, s->stream, flag);
+  if (nonfinite_dev) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, s->stream, nonfinite_dev);
+  const double *dx = (const double *)(s->ws + s->o_dx);
+  if (s->mixed())
+    hipLaunchKernelGGL(mass_kernel<float>, dim3(n_ch), dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans, a.ch_V,
+                       a.n_ch, a.scaled, (const float *)s->fA(), (const int16_t *)s->lA(), (const float *)s->cA(),
+                       hc, dx, mass_dev, nonfinite_dev, flag);
+  else
+    hipLaunchKernelGGL(mass_kernel<double>, dim3(n_ch), dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans, a.ch_V,
+                       a.n_ch, a.scaled, (const double *)s->fA(), (const int16_t *)nullptr, (const double *)s->cA(),
+                       hc, dx, mass_dev, nonfinite_dev, flag);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(s->flag_host, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipEventRecord(s->ev_flag, s->stream));
+  s->flag_pending = true;
   return HHLB_OK;
 }
 

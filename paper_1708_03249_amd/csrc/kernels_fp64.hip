@@ -1,0 +1,32 @@
+// FP64 stage kernels: half-range (two waves per window) and full-range.
+#include "launch.hpp"
+
+namespace hhlb {
+namespace {
+
+template <int QUAD, int Q, int NF, int ADV>
+void launch_stage(const StageArgs &a, hipStream_t s) {
+  if constexpr (QUAD == 0)
+    hipLaunchKernelGGL((stage_kernel_half<Q, NF, ADV>), dim3(a.nwin), dim3(128), 0, s, a, a.tb, a.chans,
+                       a.wins, a.inv_dx, a.gw, (const double *)a.in_f, (const double *)a.in_c);
+  else
+    hipLaunchKernelGGL((stage_kernel<QUAD, Q, NF, ADV>), dim3(a.nwin), dim3(64), 0, s, a);
+}
+
+template <int QUAD, int Q>
+void add(LaunchMap &m) {
+  m[{QUAD, Q, 1, 0, 0}] = launch_stage<QUAD, Q, 1, 0>;
+  m[{QUAD, Q, 1, 1, 0}] = launch_stage<QUAD, Q, 1, 1>;
+  m[{QUAD, Q, 2, 0, 0}] = launch_stage<QUAD, Q, 2, 0>;
+  m[{QUAD, Q, 2, 1, 0}] = launch_stage<QUAD, Q, 2, 1>;
+}
+
+}  // namespace
+
+void register_fp64(LaunchMap &m) {
+  add<0, 1>(m); add<0, 2>(m); add<0, 3>(m); add<0, 4>(m);
+  add<0, 6>(m); add<0, 8>(m); add<0, 12>(m); add<0, 16>(m);
+  add<1, 2>(m); add<1, 4>(m); add<1, 8>(m); add<1, 16>(m);
+}
+
+}  // namespace hhlb

@@ -1,0 +1,23 @@
+// Registry of the stage-kernel launchers, keyed by model shape and arithmetic
+// form.  Each kernel family is instantiated in its own translation unit.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <tuple>
+
+#include "step_kernels.hpp"
+
+namespace hhlb {
+
+using Launcher = void (*)(const StageArgs &, hipStream_t);
+// (quadrature kind, Q, functions (1 = f, 2 = f and chi), advection, precision)
+using LaunchKey = std::tuple<int, int, int, int, int>;
+using LaunchMap = std::map<LaunchKey, Launcher>;
+
+void register_fp64(LaunchMap &m);
+void register_mixed_f32(LaunchMap &m);
+void register_mixed_bf16(LaunchMap &m);
+void register_mixed_f16(LaunchMap &m);
+
+}  // namespace hhlb

@@ -1,0 +1,539 @@
+// gfx950 kernel for one TVD RK-3 stage of the half-range model in mixed
+// precision.  The populations are kept as phi_k = f_k / w_k (and
+// chi_k / w_k), which keeps every stored value of order one whatever the
+// node weight.  Advection (WENO-5 / upwind-3), collision, the force
+// contraction and the RK-3 combination run in FP32 arithmetic; the moment
+// sums, the wall-density flux balance of Eq. (nplus_def) and the
+// equilibrium coefficients stay in FP64.
+//
+// Storage.  A state rounded to FP32 at every step would lose the part of
+// each step's increment below half an ulp, the same part every step once the
+// flow is nearly steady: the slow modes then settle off the FP64 solution by
+// about eps / (dt lambda) and the conserved mass drifts linearly.  So
+//  * y^n is stored as an FP32 value hi plus a 16-bit correction word lo,
+//    a fixed-point fraction of hi's ulp (y = hi + lo 2^(e-39) for
+//    hi = m 2^e, m in [1/2, 1)), which carries y^n to about 2^-39;
+//  * the two RK stage buffers hold increments, d1 = y1 - y^n and
+//    d2 = y2 - y^n, in FP32, so their rounding is relative to the increment;
+//  * the last stage adds (2/3)(d2 + dt L[y2]) to (hi, lo) with an exact
+//    two-sum and writes the new (hi, lo) to the other copy of a ping-pong
+//    pair (its stencil still reads the neighbours' hi).
+// With the increments, stage s computes d_out = (1 - a_s)(d_in + dt L[y_s]),
+// y_s = hi + d_in, a_s = 0, 3/4, 1/3 the weights of y^n in Eq. (rk3).  The force block -F (K y) is
+// contracted on the matrix cores: FP32 MFMA (16 x 16 x 4) for the FP32 form
+// at Q = 16, BF16 or FP16 MFMA (16 x 16 x 16, FP32 accumulation) for those
+// forms at every Q (zero-padded to 16), and FP32 VALU otherwise.
+//
+// Thread mapping as in the FP64 half-range kernel: one 128-thread block per
+// 64-cell window, wave 0 = p > 0 half, wave 1 = p < 0 half, one cell per lane.
+#pragma once
+#include "step_kernels.hpp"
+
+#ifndef HHLB_MIXED_WAVES
+#define HHLB_MIXED_WAVES 3
+#endif
+
+namespace hhlb {
+
+enum { kPrecF32 = 1, kPrecBF16 = 2, kPrecF16 = 3 };
+
+__device__ __forceinline__ float dpp_shr1f(float x) {  // lane l <- lane l-1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_shl1f(float x) {  // lane l <- lane l+1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float readlane_f(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// WENO-5 face value in FP32: the construction of the FP64 form (product-form
+// weights after an exact power-of-two rescaling, the limits of Table (weno)
+// when sigmas vanish), with thresholds for the FP32 range.  After rescaling
+// the largest q lies in [1/4, 1); a q below 1e-17 counts as vanishing, and
+// the products are regular above 1e-37, which the pairs of non-vanishing q
+// always exceed.
+__device__ __forceinline__ float weno5f(float a, float b, float c, float d, float e) {
+  const float k13 = 13.0f / 12.0f;
+  float t1 = a - 2.0f * b + c, t2 = a - 4.0f * b + 3.0f * c;
+  const float s1 = k13 * t1 * t1 + 0.25f * t2 * t2;
+  t1 = b - 2.0f * c + d; t2 = b - d;
+  const float s2 = k13 * t1 * t1 + 0.25f * t2 * t2;
+  t1 = c - 2.0f * d + e; t2 = 3.0f * c - 4.0f * d + e;
+  const float s3 = k13 * t1 * t1 + 0.25f * t2 * t2;
+  const float F1 = 2.0f * a - 7.0f * b + 11.0f * c;
+  const float F2 = -b + 5.0f * c + 2.0f * d;
+  const float F3 = 2.0f * c + 5.0f * d - e;
+  const int ex = __builtin_amdgcn_frexp_expf(fmaxf(s1, fmaxf(s2, s3)));
+  const float r1 = ldexpf(s1, -ex), r2 = ldexpf(s2, -ex), r3 = ldexpf(s3, -ex);
+  const float q1s = r1 * r1, q2s = r2 * r2, q3s = r3 * r3;
+  const float p1 = 0.1f * q2s * q3s, p2 = 0.6f * q1s * q3s, p3 = 0.3f * q1s * q2s;
+  const float den = p1 + p2 + p3;
+  const float tiny = 1e-17f;
+  const float z1 = q1s < tiny ? 0.1f : 0.0f, z2 = q2s < tiny ? 0.6f : 0.0f, z3 = q3s < tiny ? 0.3f : 0.0f;
+  const bool regular = den > 1e-37f;
+  const float n1 = regular ? p1 : z1, n2 = regular ? p2 : z2, n3 = regular ? p3 : z3;
+  // 1/6 of the candidate stencils folded into the normalisation
+  const float inv = __builtin_amdgcn_rcpf(6.0f * (regular ? den : z1 + z2 + z3));
+  return (n1 * F1 + n2 * F2 + n3 * F3) * inv;
+}
+
+// Correction word of y = hi + lo: lo counts 2^-15 ulps of hi (|lo| <= 2^14).
+__device__ __forceinline__ float lo_value(float hi, int16_t lo) {
+  return ldexpf((float)lo, __builtin_amdgcn_frexp_expf(hi) - 39);
+}
+// y^n + delta -> (hi', lo'): the FP32 sum, and its exact rounding error
+// (two-sum) stored as the correction word.
+__device__ __forceinline__ void add_to_state(float hi, int16_t lo, float delta, float &hi_out, int16_t &lo_out) {
+  const float t = lo_value(hi, lo) + delta;
+  const float s = hi + t;
+  const float bb = s - hi;
+  const float e = (hi - (s - bb)) + (t - bb);
+  hi_out = s;
+  // |e| <= ulp(s)/2 gives |lo| <= 2^14 for normal s; the clamp only guards
+  // denormal sums
+  const float q = __builtin_rintf(ldexpf(e, 39 - __builtin_amdgcn_frexp_expf(s)));
+  lo_out = (int16_t)fminf(fmaxf(q, -32767.0f), 32767.0f);
+}
+
+template <int ADV>
+__device__ __forceinline__ float face_value_f(float a, float b, float c, float d, float e) {
+  if constexpr (ADV == 0) return weno5f(a, b, c, d, e);
+  else return (-b + 5.0f * c + 2.0f * d) * (1.0f / 6.0f);
+}
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short bfx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 hfx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+// The value an operand has once rounded for the matrix cores.
+template <int PREC>
+__device__ __forceinline__ float operand_value(float x) {
+  if constexpr (PREC == kPrecBF16) return __uint_as_float((uint32_t)(uint16_t)to_bf16(x) << 16);
+  else if constexpr (PREC == kPrecF16) return (float)(_Float16)x;
+  else return x;
+}
+
+// A operand of the force block for the matrix cores, built once per wave
+// from the FP32 table Ks (H x H, row-major), zero outside the H x H block.
+// Register layouts (checked on the GPU):
+//   16x16x4 f32:        A[i][k] in lane i + 16 k (k < 4 per instruction)
+//   16x16x16 bf16/f16:  A[i][k] in lane i + 16 (k / 4), element k % 4
+//   both:               B[k][j] like A with j for i; D[i][j] in lane
+//                       j + 16 (i / 4), accumulator register i % 4
+template <int PREC>
+struct ForceA;
+template <>
+struct ForceA<kPrecF32> {
+  float v[4];
+  template <int H>
+  __device__ __forceinline__ void load(const float *Ks, int lane) {
+    const int i = lane & 15;
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const int k = 4 * kc + (lane >> 4);
+      v[kc] = (i < H && k < H) ? Ks[(i < H ? i : 0) * H + (k < H ? k : 0)] : 0.0f;
+    }
+  }
+};
+template <>
+struct ForceA<kPrecBF16> {
+  bfx4 v;
+  template <int H>
+  __device__ __forceinline__ void load(const float *Ks, int lane) {
+    const int i = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = 4 * (lane >> 4) + t;
+      v[t] = to_bf16((i < H && k < H) ? Ks[(i < H ? i : 0) * H + (k < H ? k : 0)] : 0.0f);
+    }
+  }
+};
+template <>
+struct ForceA<kPrecF16> {   // loaded from the row-scaled table Ks16
+  hfx4 v;
+  template <int H>
+  __device__ __forceinline__ void load(const float *Ks, int lane) {
+    const int i = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = 4 * (lane >> 4) + t;
+      v[t] = (_Float16)((i < H && k < H) ? Ks[(i < H ? i : 0) * H + (k < H ? k : 0)] : 0.0f);
+    }
+  }
+};
+
+// OUT[i] = sum_k M[i][k] X[k] (i, k < H) for the 64 cells of the wave (one
+// per lane), as four 16-cell products on the matrix cores.  The cell-major
+// values go through the wave's padded LDS tile T (64 x 17 floats) into the
+// B layout and back.
+template <int PREC, int H>
+__device__ __forceinline__ void mfma_force(const ForceA<PREC> &aM, const float X[H], float OUT[H], float *T,
+                                           int lane) {
+  constexpr int S = 17;
+#pragma unroll
+  for (int k = 0; k < H; ++k) T[lane * S + k] = X[k];
+  __builtin_amdgcn_wave_barrier();
+  flt4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    acc[cb] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+    const float *row = T + (16 * cb + (lane & 15)) * S;
+    if constexpr (PREC == kPrecF32) {
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const int k = 4 * kc + (lane >> 4);
+        const float b = k < H ? row[k < H ? k : 0] : 0.0f;
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aM.v[kc], b, acc[cb], 0, 0, 0);
+      }
+    } else {
+      float bv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = 4 * (lane >> 4) + t;
+        bv[t] = k < H ? row[k < H ? k : 0] : 0.0f;
+      }
+      if constexpr (PREC == kPrecBF16) {
+        bfx4 b;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[t] = to_bf16(bv[t]);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aM.v, b, acc[cb], 0, 0, 0);
+      } else {
+        hfx4 b;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[t] = (_Float16)bv[t];
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(aM.v, b, acc[cb], 0, 0, 0);
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[(16 * cb + (lane & 15)) * S + 4 * (lane >> 4) + r] = acc[cb][r];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int k = 0; k < H; ++k) OUT[k] = T[lane * S + k];
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int Q, int NFUN, int ADV, int PREC>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_WAVES))) void stage_kernel_mixed(
+    StageArgs A, const DevTables *__restrict__ tb, const DevChannel *__restrict__ chans,
+    const DevWindow *__restrict__ wins, const double *__restrict__ inv_dx,
+    const double *__restrict__ gw, const float *__restrict__ hi_f, const float *__restrict__ hi_c,
+    const float *__restrict__ d_f, const float *__restrict__ d_c) {
+  constexpr int H = Q;
+  constexpr int NC = NFUN;
+  constexpr bool kMfmaEq = HHLB_MFMA && (H == 16);                          // FP64 equilibrium table
+  constexpr bool kMfmaK = PREC != kPrecF32 || (HHLB_MFMA && H == 16);       // force block
+  __shared__ double s_part[2][6][64];
+  __shared__ double s_nw[2];
+  // per-wave transpose tiles: 64 x 17 doubles for the FP64 equilibrium
+  // table, 64 x 17 floats when only the force block uses the matrix cores
+  __shared__ double s_T[kMfmaEq ? 2 * 64 * 17 : (kMfmaK ? 64 * 17 : 1)];
+  const int hw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int w = xcd_window(blockIdx.x, A.nwin);
+  const DevWindow win = wins[w];
+  const DevChannel C = chans[win.ch];
+  const int Nx = C.Nx;
+  const int i = win.i0 - kHalo + lane;
+  const bool inside = i >= 0 && i < Nx;
+  const int kb0 = hw * H;
+  const float sg = hw ? -1.0f : 1.0f;
+  // stage value y_s = hi + d_in (d_in = 0 in the first stage)
+  const bool has_d = A.stage != 0;
+  const int64_t rbase = C.off + (int64_t)kb0 * Nx;
+  float yf[H], yc[NC > 1 ? H : 1];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const int64_t o = rbase + (int64_t)j * Nx + i;
+    yf[j] = inside ? hi_f[o] + (has_d ? d_f[o] : 0.0f) : 0.0f;
+  }
+  if constexpr (NC > 1) {
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const int64_t o = rbase + (int64_t)j * Nx + i;
+      yc[j] = inside ? hi_c[o] + (has_d ? d_c[o] : 0.0f) : 0.0f;
+    }
+  }
+
+  // ---- closure, part 1: incoming ghosts (quadratic extrapolation) and the
+  // wall density from the incoming wall-face fluxes, balanced in FP64 ----
+  const bool needL = win.i0 < kHalo;
+  const bool needR = win.i0 - kHalo + 63 >= Nx;
+  double nw_mine = 0.0;
+  if ((hw == 1 && needL) || (hw == 0 && needR)) {
+    const bool left = hw == 1;
+    const int l0 = left ? kHalo : Nx - 1 - (win.i0 - kHalo);
+    const int dl = left ? 1 : -1;
+    const int gi = left ? -i : i - Nx + 1;
+    const float c0 = gi == 1 ? 3.0f : (gi == 2 ? 6.0f : 10.0f);
+    const float c1 = gi == 1 ? -3.0f : (gi == 2 ? -8.0f : -15.0f);
+    const float c2 = gi == 1 ? 1.0f : (gi == 2 ? 3.0f : 6.0f);
+    const bool is_ghost = gi >= 1 && gi <= 3;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const float y0 = readlane_f(yf[j], l0), y1 = readlane_f(yf[j], l0 + dl),
+                  y2 = readlane_f(yf[j], l0 + 2 * dl);
+      if (lane == j) { a0 = y0; a1 = y1; a2 = y2; }
+      if (is_ghost) yf[j] = c0 * y0 + c1 * y1 + c2 * y2;
+      if constexpr (NC > 1) {
+        const float x0 = readlane_f(yc[j], l0), x1 = readlane_f(yc[j], l0 + dl),
+                    x2 = readlane_f(yc[j], l0 + 2 * dl);
+        if (is_ghost) yc[j] = c0 * x0 + c1 * x1 + c2 * x2;
+      }
+    }
+    const double d0 = a0, d1 = a1, d2 = a2;
+    const double g1 = 3.0 * d0 - 3.0 * d1 + d2, g2 = 6.0 * d0 - 8.0 * d1 + 3.0 * d2;
+    const double fv = face_value<ADV>(d2, d1, d0, g1, g2);
+    // flux p_k f_k = (w_k p_k) phi_k, with the FP32 velocities of the
+    // advection so that the balance holds for the fluxes the stage applies
+    const double acc = wave_sum(lane < H ? tb->wpfq[kb0 + (lane < H ? lane : 0)] * fv : 0.0);
+    nw_mine = -acc * (left ? C.inv_DL : C.inv_DR);
+  }
+
+  // ---- partial moments of this half (FP64) and the rank-1 projections ----
+  double pn = 0.0, pm = 0.0, ps = 0.0, pc = 0.0, pbf = 0.0, pbc = 0.0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double y = yf[j];
+    pn += tb->wq[j] * y;
+    pm += tb->wpq[kb0 + j] * y;
+    ps += tb->wp2q[kb0 + j] * y;
+    pbf += tb->kbs[j] * y;
+    if constexpr (NC > 1) {
+      const double x = yc[j];
+      pc += tb->wq[j] * x;
+      pbc += tb->kbs[j] * x;
+    }
+  }
+  s_part[hw][0][lane] = pn;
+  s_part[hw][1][lane] = pm;
+  s_part[hw][2][lane] = ps;
+  s_part[hw][3][lane] = pc;
+  s_part[hw][4][lane] = pbf;
+  s_part[hw][5][lane] = pbc;
+  if (lane == 0) s_nw[hw] = nw_mine;
+  __syncthreads();
+  double n = s_part[0][0][lane] + s_part[1][0][lane];
+  double mom = s_part[0][1][lane] + s_part[1][1][lane];
+  const double s2 = s_part[0][2][lane] + s_part[1][2][lane];
+  const double ech = s_part[0][3][lane] + s_part[1][3][lane];
+  const float bf = (float)(s_part[0][4][lane] + s_part[1][4][lane]);
+  const float bc = (float)(s_part[0][5][lane] + s_part[1][5][lane]);
+  const double nL = s_nw[1], nR = s_nw[0];
+
+  // ---- closure, part 2: emergent ghosts phi = n_w g^w_k / w_k ----
+  if (hw == 0 && i < 0) {
+    const double *gwL = gw + C.gw_off;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const double ph = nL * gwL[j] * tb->iwq[j];
+      yf[j] = (float)ph;
+      if constexpr (NC > 1) yc[j] = (float)(C.half_Dt * C.TL * ph);
+    }
+  }
+  if (hw == 1 && i >= Nx && i <= Nx + 2) {
+    const double *gwR = gw + C.gw_off + 2 * H + H;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const double ph = nR * gwR[j] * tb->iwq[j];
+      yf[j] = (float)ph;
+      if constexpr (NC > 1) yc[j] = (float)(C.half_Dt * C.TR * ph);
+    }
+  }
+  if (A.nwall && A.stage == 2 && lane == 0) {
+    if (hw == 1 && win.i0 == 0) A.nwall[2 * win.ch] = nL;
+    if (hw == 0 && win.i0 <= Nx - 1 && Nx - 1 < win.i0 + kWin) A.nwall[2 * win.ch + 1] = nR;
+  }
+
+  // ---- moments (Eq. fmoms), FP64 ----
+  if (!inside) n = 1.0, mom = 0.0;
+  const double u = mom / n;
+  double T = (s2 - u * mom + 2.0 * ech) * C.inv_1pDt / n;
+  if (!inside) T = 1.0;
+
+  // ---- equilibrium coefficients of this half (FP64, as in the FP64 form) ----
+  double G[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) G[l] = 0.0;
+  const bool collide = C.inv_Kn != 0.0;
+  if (collide) {
+    const double sT = sqrt(T);
+    const double ub = (hw ? -u : u) * tb->inv_p0, s = sT * tb->inv_p0, y0 = -u / sT;
+    auto accum = [&](double x, double wt) {
+      double qm = 1.0, q = x - tb->a[0];
+      G[0] += wt;
+      if (Q > 1) G[1] += wt * q;
+#pragma unroll
+      for (int l = 1; l + 1 < Q; ++l) {
+        const double qn = (x - tb->a[l]) * q - tb->mb[l] * qm;
+        qm = q; q = qn;
+        G[l + 1] += wt * q;
+      }
+    };
+#pragma unroll 1
+    for (int j = 0; j < tb->nm; ++j) accum(ub + s * tb->zm[j], tb->wm[j]);
+    const double ymax = wave_max(inside ? fabs(y0) : 0.0);
+    if (ymax > 0.0) {
+      int li = kLadder - 1;
+      for (int j = 1; j < kLadder; ++j)
+        if (tb->lad_y[j] >= ymax) { li = j; break; }
+      const int nc = tb->lad_n[li], o = tb->lad_off[li];
+      const double sgd = hw ? -1.0 : 1.0;
+      for (int j = 0; j < nc; ++j) {
+        const double t = tb->ltau[o + j];
+        const double yt = y0 * t;
+        const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
+        accum(ub * (1.0 - t), -sgd * e);
+      }
+    }
+  }
+
+  const bool out_lane = lane >= kHalo && lane < kHalo + kWin && inside;
+  const int ic = inside ? i : 0;
+  const float dx_inv = (float)inv_dx[C.cell_off + ic];
+  const int64_t obase = C.off + (int64_t)kb0 * Nx;
+  const float gforce = (float)C.g, dt = (float)C.dt;
+  const bool wall_face = hw == 0 ? (i == -1) : (i == Nx - 1);
+
+  // pass 1: local sources in FP32: -F (K y)_k - (y_k - y^eq_k)/tau
+  float srcf[H], srcc[NC > 1 ? H : 1];
+  {
+    // BGK term (y_k - y^eq_k)/tau formed in FP64 and rounded once: a rounded
+    // y^eq would bias the collision's mass, momentum and energy by one
+    // rounding of the equilibrium per step, the same each step in a steady
+    // state, while this keeps the error relative to y - y^eq
+    float colf[H], colc[NC > 1 ? H : 1];
+    const double itau = n * C.inv_Kn, eqc = C.half_Dt * T;
+    auto bgk = [&](int j, double geq) {
+      const double fe = n * geq;
+      colf[j] = (float)(((double)yf[j] - fe) * itau);
+      if constexpr (NC > 1) colc[j] = (float)(((double)yc[j] - eqc * fe) * itau);
+    };
+    if constexpr (kMfmaEq) {
+      double aH[4];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) aH[kc] = tb->HWss[(lane & 15) * Q + 4 * kc + (lane >> 4)];
+      double geq[H];
+      mfma_contract16(aH, G, geq, s_T + hw * 64 * 17, lane);
+#pragma unroll
+      for (int j = 0; j < H; ++j) bgk(j, geq[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) acc += tb->HWss[j * Q + l] * G[l];
+        bgk(j, acc);
+      }
+    }
+    float ky[H];
+    if constexpr (kMfmaK) {
+      ForceA<PREC> aK;
+      aK.template load<H>(PREC == kPrecF16 ? tb->Ks16 : tb->Ks, lane);
+      float *Tw = (float *)s_T + hw * (kMfmaEq ? 2 : 1) * 64 * 17;
+#pragma unroll
+      for (int fn = 0; fn < NC; ++fn) {
+        const float *y = fn == 0 ? yf : yc;
+        if constexpr (PREC == kPrecF32) {
+          mfma_force<PREC, H>(aK, y, ky, Tw, lane);
+        } else {
+          // FP16: scale the cell by a power of two so that max |y| < 1
+          float sc = 1.0f, isc = 1.0f;
+          if constexpr (PREC == kPrecF16) {
+            float m = 0.0f;
+#pragma unroll
+            for (int j = 0; j < H; ++j) m = fmaxf(m, fabsf(y[j]));
+            const int e = __builtin_amdgcn_frexp_expf(m);
+            sc = ldexpf(1.0f, -e);
+            isc = ldexpf(1.0f, e);
+          }
+          float ys[H];
+          float d = 0.0f;   // mass defect of the rounded block: sum_j crs_j yr_j
+#pragma unroll
+          for (int j = 0; j < H; ++j) {
+            ys[j] = y[j] * sc;
+            d += tb->crs[j] * operand_value<PREC>(ys[j]);
+          }
+          mfma_force<PREC, H>(aK, ys, ky, Tw, lane);
+          const float dc = d * isc * tb->iwh;
+#pragma unroll
+          for (int j = 0; j < H; ++j) {
+            const float o = PREC == kPrecF16 ? ky[j] * tb->irsc[j] : ky[j];
+            ky[j] = o * isc - dc;
+          }
+        }
+        const float bb = fn == 0 ? bf : bc;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+          if (fn == 0) srcf[j] = -gforce * sg * (ky[j] + tb->kas[j] * bb) - colf[j];
+          else if constexpr (NC > 1) srcc[j] = -gforce * sg * (ky[j] + tb->kas[j] * bb) - colc[j];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        float kf = 0.0f, kc = 0.0f;
+#pragma unroll
+        for (int jj = 0; jj < H; ++jj) {
+          const float kv = tb->Ks[j * H + jj];
+          kf += kv * yf[jj];
+          if constexpr (NC > 1) kc += kv * yc[jj];
+        }
+        srcf[j] = -gforce * sg * (kf + tb->kas[j] * bf) - colf[j];
+        if constexpr (NC > 1) srcc[j] = -gforce * sg * (kc + tb->kas[j] * bc) - colc[j];
+      }
+    }
+  }
+
+  // pass 2: advection and the RK-3 combination, FP32, in increment form
+  const float b_inc = (float)A.b_stage;   // 1 - a_s
+  const bool last = A.stage == 2;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const float v = tb->pf[kb0 + j];
+#pragma unroll
+    for (int fn = 0; fn < NC; ++fn) {
+      const float y0v = fn == 0 ? yf[j] : yc[j];
+      const float src = fn == 0 ? srcf[j] : srcc[j];
+      float F;
+      if (hw == 0) {
+        const float ym1 = dpp_shr1f(y0v), ym2 = dpp_shr1f(ym1);
+        const float yp1 = dpp_shl1f(y0v), yp2 = dpp_shl1f(yp1);
+        F = v * face_value_f<ADV>(ym2, ym1, y0v, yp1, yp2);
+        if (wall_face) F = v * y0v;
+      } else {
+        const float ym1 = dpp_shr1f(y0v);
+        const float yp1 = dpp_shl1f(y0v), yp2 = dpp_shl1f(yp1), yp3 = dpp_shl1f(yp2);
+        F = v * face_value_f<ADV>(yp3, yp2, yp1, y0v, ym1);
+        if (wall_face) F = v * yp1;
+      }
+      const float Fl = dpp_shr1f(F);
+      const float L = -(F - Fl) * dx_inv + src;
+      const int64_t o = obase + (int64_t)j * Nx + ic;
+      const float din = has_d ? (fn == 0 ? d_f : d_c)[o] : 0.0f;
+      const float inc = b_inc * (din + dt * L);
+      if (!last) {
+        if (out_lane) ((float *)(fn == 0 ? A.out_f : A.out_c))[o] = inc;
+      } else {
+        const float hi = (fn == 0 ? hi_f : hi_c)[o];
+        const int16_t lo = (fn == 0 ? A.lo_in_f : A.lo_in_c)[o];
+        float hn;
+        int16_t ln;
+        add_to_state(hi, lo, inc, hn, ln);
+        if (out_lane) {
+          ((float *)(fn == 0 ? A.out_f : A.out_c))[o] = hn;
+          (fn == 0 ? A.lo_out_f : A.lo_out_c)[o] = ln;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+}  // namespace hhlb

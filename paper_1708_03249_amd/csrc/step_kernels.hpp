@@ -52,6 +52,27 @@ struct DevTables {
   // M = ceil((N+1)/2), exact for the degree-N integrands
   int nm;
   double zm[kQmaxDev], wm[kQmaxDev];
+  // mixed-precision form: the state is kept as phi_k = f_k / w_k, so the
+  // half-range tables are rescaled by the node weights
+  double wq[kQmaxDev], iwq[kQmaxDev];     // w_k, 1/w_k of a half
+  double wpq[2 * kQmaxDev];               // w_k p_k/m (both halves)
+  double wpfq[2 * kQmaxDev];              // w_k (p_k/m rounded to FP32): the wall-flux balance uses
+                                          // the velocities the FP32 advection uses
+  double wp2q[2 * kQmaxDev];              // w_k (p_k/m)^2
+  double kbs[kQmaxDev];                   // kb_j w_j
+  double HWss[kQmaxDev * kQmaxDev];       // HWs[k][l] / w_k
+  float Ks[kQmaxDev * kQmaxDev];          // Kin[k][j] w_j / w_k
+  float kas[kQmaxDev];                    // ka_k / w_k
+  float pf[2 * kQmaxDev];                 // p_k/m
+  // reduced-precision force operands (BF16 / FP16 forms): the FP16 table is
+  // Ks with row k scaled by rsc_k (a power of two, |row| <= 1) and irsc_k =
+  // 1/rsc_k; crs_j = sum_k w_k Kr_kj are the weighted column sums of the
+  // table exactly as the matrix cores see it (Kr), whose mass defect the
+  // kernel removes; iwh = 1 / sum over a half of w_k
+  float Ks16[kQmaxDev * kQmaxDev];
+  float irsc[kQmaxDev];
+  float crs[kQmaxDev];
+  float iwh;
 };
 
 // Per channel.
@@ -65,7 +86,7 @@ struct DevChannel {
   double inv_Kn;      // 1/Kn (0 when collisionless)
   double dt;
   double TL, TR;      // wall temperatures
-  double inv_DL;      // 1 / sum_{p_k>0} (p_k/m) gwL_k
+  double inv_DL;      // 1 / sum_{p_k>0} (p_k/m) gwL_k  (mixed form: p_k/m rounded to FP32)
   double inv_DR;      // 1 / sum_{p_k<0} (p_k/m) gwR_k
   double half_Dt;     // Dt/2
   double inv_1pDt;    // 1/(1+Dt)
@@ -85,11 +106,16 @@ struct StageArgs {
   int32_t stage;             // 0, 1, 2 (only stage 2 writes the wall densities)
   const double *inv_dx;      // per cell
   const double *gw;          // wall equilibria
-  const double *in_f, *in_c; // stage state
-  const double *base_f, *base_c;  // y^n (pointwise)
-  double *out_f, *out_c;
+  // state arrays: double (FP64 form) or float (mixed form)
+  const void *in_f, *in_c;   // stage state
+  const void *base_f, *base_c;  // y^n (pointwise)
+  void *out_f, *out_c;
   double a_base, b_stage;    // out = a_base * y^n + b_stage * (y_s + dt L[y_s])
   double *nwall;             // 2 per channel (may be null)
+  // mixed form only: 16-bit correction words of y^n (read in the last stage)
+  // and of y^{n+1} (written there)
+  const int16_t *lo_in_f, *lo_in_c;
+  int16_t *lo_out_f, *lo_out_c;
 };
 
 __device__ __forceinline__ double dpp_shr1(double x) {  // lane l <- lane l-1
@@ -213,8 +239,8 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs A) {
   const int Nx = C.Nx;
   const int i = win.i0 - kHalo + lane;
   const bool inside = i >= 0 && i < Nx;
-  const double *fin = A.in_f + C.off;
-  const double *cin = NC > 1 ? A.in_c + C.off : nullptr;
+  const double *fin = (const double *)A.in_f + C.off;
+  const double *cin = NC > 1 ? (const double *)A.in_c + C.off : nullptr;
 
   double yf[V], yc[NC > 1 ? V : 1];
 #pragma unroll
@@ -366,10 +392,10 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs A) {
 
   const bool out_lane = lane >= kHalo && lane < kHalo + kWin && inside;
   const double dx_inv = inside ? A.inv_dx[C.cell_off + i] : 0.0;
-  const double *bfp = A.base_f + C.off;
-  double *ofp = A.out_f + C.off;
-  const double *bcp = NC > 1 ? A.base_c + C.off : nullptr;
-  double *ocp = NC > 1 ? A.out_c + C.off : nullptr;
+  const double *bfp = (const double *)A.base_f + C.off;
+  double *ofp = (double *)A.out_f + C.off;
+  const double *bcp = NC > 1 ? (const double *)A.base_c + C.off : nullptr;
+  double *ocp = NC > 1 ? (double *)A.out_c + C.off : nullptr;
   const double gforce = C.g, dt = C.dt;
   const bool lwall_face = (i == -1), rwall_face = (i == Nx - 1);
 
@@ -725,8 +751,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
       const double Fl = dpp_shr1(F);
       const double L = -(F - Fl) * dx_inv + src;
       const int64_t o = obase + (int64_t)j * Nx + ic;
-      const double *bp = fn == 0 ? A.base_f : A.base_c;
-      double *op = fn == 0 ? A.out_f : A.out_c;
+      const double *bp = (const double *)(fn == 0 ? A.base_f : A.base_c);
+      double *op = (double *)(fn == 0 ? A.out_f : A.out_c);
       const double base = A.a_base != 0.0 ? bp[o] : 0.0;
       const double yn = A.a_base * base + A.b_stage * (y0v + dt * L);
       if (out_lane) op[o] = yn;

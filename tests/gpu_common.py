@@ -33,10 +33,10 @@ def initial_states(channels, seed=0, perturb=0.0, n0=1.0, u0=0.0, T0=1.0):
     return out
 
 
-def run_gpu(channels, states, nsteps):
+def run_gpu(channels, states, nsteps, precision=0):
     import torch
     import paper_1708_03249_amd as H
-    s = H.Solver(channels)
+    s = H.Solver(channels, precision=precision)
     f = torch.from_numpy(np.concatenate([st[0].ravel() for st in states])).cuda()
     c = torch.from_numpy(np.concatenate([st[1].ravel() for st in states])).cuda()
     s.set_state(f, c if s.has_chi else None)
@@ -90,3 +90,32 @@ def compare(channels, gpu, ref, tol=1e-12, what=""):
     bad = {k: v for k, v in worst.items() if not v <= tol}
     assert not bad, f"{what}: parity beyond {tol}: {worst}"
     return worst
+
+
+def moment_errors(channels, gpu, ref):
+    """Errors of the moments against the oracle: err_n = max|dn| / max n,
+    err_T = max|dT| / max T, err_u = max|du| / sqrt(T_left/m), each the
+    worst over the channels in ref."""
+    e = dict(n=0.0, u=0.0, T=0.0)
+    for c, r in ref.items():
+        a0, a1 = gpu["cells"][c], gpu["cells"][c + 1]
+        e["n"] = max(e["n"], np.max(np.abs(gpu["n"][a0:a1] - r["n"])) / np.max(r["n"]))
+        e["T"] = max(e["T"], np.max(np.abs(gpu["T"][a0:a1] - r["T"])) / np.max(r["T"]))
+        e["u"] = max(e["u"], np.max(np.abs(gpu["u"][a0:a1] - r["u"])) / math.sqrt(channels[c].T_left))
+    return e
+
+
+def load_golden(path):
+    """(f, chi, n_wall) of a stored oracle result."""
+    rows = {"f": [], "chi": []}
+    nwall = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            tag, *vals = line.split()
+            if tag == "nwall":
+                nwall = np.array([float(v) for v in vals])
+            else:
+                rows[tag].append([float(v) for v in vals])
+    return np.array(rows["f"]), np.array(rows["chi"]), nwall

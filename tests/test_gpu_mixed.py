@@ -1,0 +1,185 @@
+"""GPU checks of the mixed-precision forms against the FP64 oracle.
+
+The FP32 form (FP32 state f/w_k, FP32 advection, collision and force, FP64
+moments, wall flux and equilibrium coefficients) must match the oracle's
+n, u, T within 1e-5 (err_n = max|dn|/max n, err_T = max|dT|/max T,
+err_u = max|du|/sqrt(T_left)).  The BF16 and FP16 forms (force block from
+BF16 / FP16 operands on the matrix cores) have no stated error target: their
+errors are measured and reported, and checked against a loose bound that a
+wrong operand layout or a lost mass defect would exceed.  Mass stays exact to
+rounding in every form.  Set HHLB_REPORT_DIR to write the precision table
+of the small-channel workload (20 000 steps per Kn) as JSON."""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_common import initial_states, load_golden, moment_errors, run_gpu, run_oracle  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+# loose bound for the BF16 / FP16 force forms (measured errors are listed in
+# the design notes; a transposed operand gives errors of order 1e-2)
+TOL_REDUCED = 2e-3
+FORMS = ("mixed_f32", "mixed_bf16", "mixed_f16")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1708_03249_amd as H
+    H.lib()
+
+
+def H():
+    import paper_1708_03249_amd as H
+    return H
+
+
+def _cases():
+    h = H()
+    return {
+        "stretched HHLB(7;8) WENO-5, Kn 0.01/0.1/1": (
+            [h.Channel(quad=h.HALF_HERMITE, Q=8, Nx=200, adv=h.WENO5, stretch_A=0.9, T_left=1.0,
+                       T_right=2.0, g=-0.5, Kn=kn, dt=-0.5) for kn in (0.01, 0.1, 1.0)], 200, 0.05),
+        "HHLB(15;16) WENO-5": (
+            [h.Channel(quad=h.HALF_HERMITE, Q=16, Nx=150, adv=h.WENO5, stretch_A=0.9, T_left=1.0,
+                       T_right=1.5, g=-1.0, Kn=0.02, dt=-0.5)], 100, 0.02),
+        "Q 4/12/6 batch, upwind-3 and WENO-5, Dt 2/0, Kn = inf": (
+            [h.Channel(quad=h.HALF_HERMITE, Q=4, Nx=64, adv=h.UPWIND3, Kn=0.1, g=-0.1, dt=5e-4),
+             h.Channel(quad=h.HALF_HERMITE, Q=12, Nx=130, adv=h.WENO5, Kn=0.05, g=-1.0, T_right=1.5,
+                       dt=-0.5),
+             h.Channel(quad=h.HALF_HERMITE, Q=6, N=3, Nx=8, adv=h.WENO5, transverse_dof=0,
+                       Kn=math.inf, g=0.3, T_left=1.2, T_right=0.8, dt=2e-4)], 300, 0.03),
+    }
+
+
+@pytest.mark.parametrize("case", list(_cases().keys()))
+def test_mixed_forms_against_oracle(case):
+    chans, nsteps, pert = _cases()[case]
+    states = initial_states(chans, seed=1, perturb=pert)
+    print(f"[mixed] {case}: {nsteps} steps", flush=True)
+    g64 = run_gpu(chans, states, nsteps)
+    ref = run_oracle(chans, states, nsteps, g64["dt"])
+    for form in FORMS:
+        g = run_gpu(chans, states, nsteps, precision=H().PRECISIONS[form])
+        assert g["bad"] == 0, form
+        e = moment_errors(chans, g, ref)
+        dm = float(np.max(np.abs(g["mass"] / g64["mass"] - 1)))
+        print(f"  {form}: err n {e['n']:.2e} u {e['u']:.2e} T {e['T']:.2e} mass {dm:.1e}", flush=True)
+        tol = TOL_F32 if form == "mixed_f32" else TOL_REDUCED
+        assert max(e.values()) <= tol, (form, e)
+        assert dm <= 1e-6, (form, dm)
+
+
+def test_mixed_mass_long_run():
+    """Mass over 3000 steps in every form: FP32 storage rounds each population
+    once per stage (a relative random walk of about 6e-8 sqrt(steps / (V Nx)))
+    and the reduced-precision force blocks have their mass defect removed, so
+    sum_i dx_i n_i stays within 1e-6 while the bias of unnormalised RK weights
+    or of a rounded force table would drift by 1e-4 or more."""
+    h = H()
+    ch = h.Channel(quad=h.HALF_HERMITE, Q=8, Nx=300, adv=h.WENO5, stretch_A=0.9, T_left=1.0,
+                   T_right=2.0, g=-0.5, Kn=0.05, dt=-0.5)
+    states = initial_states([ch], seed=4, perturb=0.05)
+    for form in FORMS:
+        g = run_gpu([ch], states, 3000, precision=h.PRECISIONS[form])
+        m0 = run_gpu([ch], states, 0, precision=h.PRECISIONS[form])["mass"][0]
+        print(f"  {form}: mass drift {abs(g['mass'][0] / m0 - 1):.1e}", flush=True)
+        assert abs(g["mass"][0] / m0 - 1) <= 1e-6, form
+
+
+def test_small_channel_precision_table():
+    """The small-channel workload (HHLB(3;4), Nx = 64, upwind-3, g = -0.1,
+    equal walls, dt = 5e-4) for 20 000 steps at Kn = 0.01, 0.1, 1 in every
+    form against the stored oracle results: FP32 within 1e-5, the BF16 / FP16
+    forms within the loose bound; the table of errors is reported."""
+    import oracle as O
+    from gpu_common import to_oracle
+    h = H()
+    here = os.path.dirname(os.path.abspath(__file__))
+    table = []
+    for kn in (0.01, 0.1, 1.0):
+        ch = h.Channel(quad=h.HALF_HERMITE, Q=4, N=3, Nx=64, adv=h.UPWIND3, transverse_dof=2,
+                       Kn=kn, g=-0.1, dt=5e-4)
+        fg, cg, _ = load_golden(os.path.join(here, "golden", f"small_channel_kn{kn:g}_20000.txt"))
+        n, u, T = O.moments(to_oracle(ch), fg, cg)
+        ref = {0: dict(n=n, u=u, T=T)}
+        states = initial_states([ch])
+        for form in ("fp64",) + FORMS:
+            print(f"[precision table] Kn={kn:g} {form}", flush=True)
+            g = run_gpu([ch], states, 20000, precision=h.PRECISIONS[form])
+            e = moment_errors([ch], g, ref)
+            table.append(dict(Kn=kn, form=form, err_n=e["n"], err_u=e["u"], err_T=e["T"],
+                              mass=float(g["mass"][0])))
+    for row in table:
+        print(f"  Kn={row['Kn']:<5g} {row['form']:10s} err_n {row['err_n']:.2e} "
+              f"err_u {row['err_u']:.2e} err_T {row['err_T']:.2e}", flush=True)
+    out = os.environ.get("HHLB_REPORT_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "precision_table_small_channel.json"), "w") as fh:
+            json.dump(table, fh, indent=1)
+    for row in table:
+        tol = {"fp64": 1e-12, "mixed_f32": TOL_F32}.get(row["form"], TOL_REDUCED)
+        assert max(row["err_n"], row["err_u"], row["err_T"]) <= tol, row
+
+
+def test_mixed_graph_replay_matches_direct_launches():
+    """The mixed form flips its ping-pong state copy every step; HIP-graph
+    replay (graphs of 16 and of 5 steps, and 1-step remainders, from either
+    parity) must give the same bits as direct launches."""
+    import torch
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=8, Nx=200, adv=h.WENO5, stretch_A=0.9,
+                       T_left=1.0, T_right=2.0, g=-0.5, Kn=kn, dt=-0.5) for kn in (0.02, 0.5)]
+    states = initial_states(chans, seed=3, perturb=0.05)
+    f0 = torch.from_numpy(np.concatenate([s[0].ravel() for s in states])).cuda()
+    c0 = torch.from_numpy(np.concatenate([s[1].ravel() for s in states])).cuda()
+    solvers = []
+    for gsteps in (0, 16, 5):
+        s = h.Solver(chans, precision=h.MIXED_BF16)
+        s.set_graph_steps(gsteps)
+        s.set_state(f0, c0)
+        solvers.append(s)
+    for rnd, n in enumerate((7, 7, 37, 1, 16, 3)):
+        outs = []
+        for s in solvers:
+            s.step(n)
+            f, c = s.get_state()
+            torch.cuda.synchronize()
+            outs.append((f.cpu().numpy(), c.cpu().numpy()))
+        for k in (1, 2):
+            assert np.array_equal(outs[0][0], outs[k][0]), f"f differs, call {rnd}, solver {k}"
+            assert np.array_equal(outs[0][1], outs[k][1]), f"chi differs, call {rnd}, solver {k}"
+    for s in solvers:
+        s.close()
+
+
+def test_mixed_state_round_trip():
+    """set_state / get_state of the mixed form keep a population to about
+    2^-39 relative (FP32 value plus the 16-bit correction word)."""
+    import torch
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=16, Nx=100, adv=h.WENO5, Kn=0.1),
+             h.Channel(quad=h.HALF_HERMITE, Q=4, Nx=70, adv=h.UPWIND3, transverse_dof=0, Kn=0.1)]
+    states = initial_states(chans, seed=9, perturb=0.3)
+    f0 = np.concatenate([s[0].ravel() for s in states])
+    c0 = np.concatenate([s[1].ravel() for s in states])
+    s = h.Solver(chans, precision=h.MIXED_F32)
+    s.set_state(torch.from_numpy(f0).cuda(), torch.from_numpy(c0).cuda())
+    f, c = s.get_state()
+    torch.cuda.synchronize()
+    f, c = f.cpu().numpy(), c.cpu().numpy()
+    s.close()
+    assert np.max(np.abs(f / f0 - 1)) < 2 ** -38
+    V0 = chans[0].V * chans[0].Nx
+    assert np.max(np.abs(c[:V0] / c0[:V0] - 1)) < 2 ** -38
+    assert np.all(c[V0:] == 0.0)   # the second channel has no chi

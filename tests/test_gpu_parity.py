@@ -153,28 +153,14 @@ def test_graph_replay_matches_direct_launches():
         s.close()
 
 
-def _load_golden(path):
-    rows = {"f": [], "chi": []}
-    nwall = None
-    with open(path) as fh:
-        for line in fh:
-            if line.startswith("#"):
-                continue
-            tag, *vals = line.split()
-            if tag == "nwall":
-                nwall = np.array([float(v) for v in vals])
-            else:
-                rows[tag].append([float(v) for v in vals])
-    return np.array(rows["f"]), np.array(rows["chi"]), nwall
-
-
 def test_small_channel_20000_steps_golden():
     """HHLB(3;4), Nx = 64, third-order upwind, Kn = 0.1, g = -0.1, equal walls,
     dt = 5e-4: 20 000 steps (t = 10, close to the steady flow) against the
-    stored oracle result (tests/golden/small_channel_20000.txt, written by
-    make_oracle_golden.py from the oracle alone)."""
+    stored oracle result (tests/golden/small_channel_kn0.1_20000.txt, written
+    by make_oracle_golden.py from the oracle alone)."""
+    from gpu_common import load_golden
     here = os.path.dirname(os.path.abspath(__file__))
-    fg, cg, nwg = _load_golden(os.path.join(here, "golden", "small_channel_20000.txt"))
+    fg, cg, nwg = load_golden(os.path.join(here, "golden", "small_channel_kn0.1_20000.txt"))
     h = H()
     ch = h.Channel(quad=h.HALF_HERMITE, Q=4, N=3, Nx=64, adv=h.UPWIND3, transverse_dof=2,
                    Kn=0.1, g=-0.1, dt=5e-4)

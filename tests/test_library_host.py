@@ -50,11 +50,11 @@ def test_host_equilibrium_lower_order():
     np.testing.assert_allclose(g, go, rtol=0, atol=2e-15)
 
 
-def _create(channels):
+def _create(channels, precision=H.FP64):
     import ctypes
     arr = (H._CChannel * len(channels))(*[c._c() for c in channels])
     h = ctypes.c_void_p()
-    st = H.lib().hhlb_create(arr, len(channels), H.FP64, None, ctypes.byref(h))
+    st = H.lib().hhlb_create(arr, len(channels), precision, None, ctypes.byref(h))
     return st, h
 
 
@@ -97,3 +97,27 @@ def test_cfl_time_step_resolution():
     oc = O.Channel(Q=8, Nx=512, A=0.9, Kn=0.01)
     assert dts[0] == pytest.approx(O.cfl_dt(oc, 0.5), rel=1e-12)
     H.lib().hhlb_destroy(h)
+
+
+def test_precision_argument_and_mixed_workspace():
+    """Unknown forms are HHLB_E_ARG; the mixed forms cover the half-range
+    model only; their state storage is 4 FP32 copies and 2 16-bit copies per
+    function (20 bytes per population against the FP64 form's 24)."""
+    import ctypes
+    ch = H.Channel(Q=8, Nx=640, Kn=0.1)
+    for bad in (-1, 4):
+        st, _ = _create([ch], precision=bad)
+        assert st == -1
+    st, _ = _create([H.Channel(quad=H.FULL_HERMITE, Q=8)], precision=H.MIXED_F32)
+    assert st == -2
+    sizes = {}
+    for prec in (H.FP64, H.MIXED_F32, H.MIXED_BF16, H.MIXED_F16):
+        st, h = _create([ch], precision=prec)
+        assert st == 0
+        nb = ctypes.c_size_t()
+        assert H.lib().hhlb_workspace_bytes(h, ctypes.byref(nb)) == 0
+        sizes[prec] = nb.value
+        H.lib().hhlb_destroy(h)
+    pops = 2 * 16 * 640   # f and chi
+    assert sizes[H.FP64] - sizes[H.MIXED_F32] == pytest.approx(pops * (24 - 20), abs=4096)
+    assert sizes[H.MIXED_F32] == sizes[H.MIXED_BF16] == sizes[H.MIXED_F16]
