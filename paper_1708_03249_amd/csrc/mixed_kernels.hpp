@@ -38,10 +38,10 @@ namespace hhlb {
 enum { kPrecF32 = 1, kPrecBF16 = 2, kPrecF16 = 3 };
 
 __device__ __forceinline__ float dpp_shr1f(float x) {  // lane l <- lane l-1
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float dpp_shl1f(float x) {  // lane l <- lane l+1
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float readlane_f(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
@@ -491,14 +491,39 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
     }
   }
 
-  // pass 2: advection and the RK-3 combination, FP32, in increment form
-  const float b_inc = (float)A.b_stage;   // 1 - a_s
+  // pass 2: advection and the RK-3 combination, FP32, in increment form.
+  // The stage increment (and, in the last stage, hi and lo of y^n) are
+  // loaded HHLB_PREFETCH node-functions ahead of their use.
   const bool last = A.stage == 2;
+  constexpr int NSEC = H * NC;
+  constexpr int PD = HHLB_PREFETCH < NSEC ? HHLB_PREFETCH : NSEC;
+  auto off_of = [&](int sec) { return obase + (int64_t)(sec / NC) * Nx + ic; };
+  float dq[PD], hq[PD];
+  int16_t lq[PD];
+  auto fetch = [&](int sec, int slot) {
+    const int64_t o = off_of(sec);
+    const bool f0 = (sec % NC) == 0;
+    dq[slot] = has_d ? (f0 ? d_f : d_c)[o] : 0.0f;
+    if (last) {
+      hq[slot] = (f0 ? hi_f : hi_c)[o];
+      lq[slot] = (f0 ? A.lo_in_f : A.lo_in_c)[o];
+    } else {
+      hq[slot] = 0.0f;
+      lq[slot] = 0;
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d) fetch(d, d);
+  const float b_inc = (float)A.b_stage;   // 1 - a_s
 #pragma unroll
   for (int j = 0; j < H; ++j) {
     const float v = tb->pf[kb0 + j];
 #pragma unroll
     for (int fn = 0; fn < NC; ++fn) {
+      const int sec = j * NC + fn;
+      const float din = dq[sec % PD], hi = hq[sec % PD];
+      const int16_t lo = lq[sec % PD];
+      if (sec + PD < NSEC) fetch(sec + PD, sec % PD);
       const float y0v = fn == 0 ? yf[j] : yc[j];
       const float src = fn == 0 ? srcf[j] : srcc[j];
       float F;
@@ -516,13 +541,10 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
       const float Fl = dpp_shr1f(F);
       const float L = -(F - Fl) * dx_inv + src;
       const int64_t o = obase + (int64_t)j * Nx + ic;
-      const float din = has_d ? (fn == 0 ? d_f : d_c)[o] : 0.0f;
       const float inc = b_inc * (din + dt * L);
       if (!last) {
         if (out_lane) ((float *)(fn == 0 ? A.out_f : A.out_c))[o] = inc;
       } else {
-        const float hi = (fn == 0 ? hi_f : hi_c)[o];
-        const int16_t lo = (fn == 0 ? A.lo_in_f : A.lo_in_c)[o];
         float hn;
         int16_t ln;
         add_to_state(hi, lo, inc, hn, ln);
@@ -531,7 +553,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
           (fn == 0 ? A.lo_out_f : A.lo_out_c)[o] = ln;
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
+      // a scheduling fence after every HHLB_SCHED_GROUP node-functions:
+      // interleaving more unrolled WENO evaluations exceeds the register file
+      if ((j * NC + fn + 1) % HHLB_SCHED_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
     }
   }
 }

@@ -27,6 +27,15 @@ constexpr int kWin = 58;       // output cells per wavefront
 #ifndef HHLB_HALF_WAVES
 #define HHLB_HALF_WAVES 3
 #endif
+// node-functions per scheduling section in the advection pass
+#ifndef HHLB_SCHED_GROUP
+#define HHLB_SCHED_GROUP 1
+#endif
+// how many node-functions ahead the advection pass loads the values of y^n
+// (and, in the mixed form, the stage increments and correction words)
+#ifndef HHLB_PREFETCH
+#define HHLB_PREFETCH 3
+#endif
 constexpr int kHalo = 3;
 
 // Per model class (quadrature, Q, N, p0): uploaded once.
@@ -120,14 +129,21 @@ struct StageArgs {
 
 __device__ __forceinline__ double dpp_shr1(double x) {  // lane l <- lane l-1
   int lo = __double2loint(x), hi = __double2hiint(x);
-  lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double dpp_shl1(double x) {  // lane l <- lane l+1
   int lo = __double2loint(x), hi = __double2hiint(x);
-  lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  lo = __builtin_amdgcn_readlane(lo, l);
+  hi = __builtin_amdgcn_readlane(hi, l);
   return __hiloint2double(hi, lo);
 }
 
@@ -449,13 +465,6 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs A) {
   }
 }
 
-__device__ __forceinline__ double readlane_d(double x, int l) {
-  int lo = __double2loint(x), hi = __double2hiint(x);
-  lo = __builtin_amdgcn_readlane(lo, l);
-  hi = __builtin_amdgcn_readlane(hi, l);
-  return __hiloint2double(hi, lo);
-}
-
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
@@ -728,12 +737,26 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
     }
   }
   // pass 2: advection (WENO-5 / upwind-3 face fluxes, Sec. IV.C.2) and the
-  // RK-3 combination
+  // RK-3 combination.  The y^n values the combination needs are loaded
+  // HHLB_PREFETCH node-functions ahead of their use, so that the memory
+  // latency overlaps the WENO arithmetic of the nodes in between.
+  constexpr int NSEC = H * NC;
+  constexpr int PD = HHLB_PREFETCH < NSEC ? HHLB_PREFETCH : NSEC;
+  const bool need_base = A.a_base != 0.0;
+  auto base_ptr = [&](int sec) {
+    return (const double *)((sec % NC) == 0 ? A.base_f : A.base_c) + obase + (int64_t)(sec / NC) * Nx + ic;
+  };
+  double bq[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) bq[d] = need_base ? *base_ptr(d) : 0.0;
 #pragma unroll
   for (int j = 0; j < H; ++j) {
     const double v = tb->p[kb0 + j];
 #pragma unroll
     for (int fn = 0; fn < NC; ++fn) {
+      const int sec = j * NC + fn;
+      const double base = bq[sec % PD];
+      if (sec + PD < NSEC) bq[sec % PD] = need_base ? *base_ptr(sec + PD) : 0.0;
       const double y0v = fn == 0 ? yf[j] : yc[j];
       const double src = fn == 0 ? srcf[j] : srcc[j];
       double F;
@@ -751,14 +774,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
       const double Fl = dpp_shr1(F);
       const double L = -(F - Fl) * dx_inv + src;
       const int64_t o = obase + (int64_t)j * Nx + ic;
-      const double *bp = (const double *)(fn == 0 ? A.base_f : A.base_c);
       double *op = (double *)(fn == 0 ? A.out_f : A.out_c);
-      const double base = A.a_base != 0.0 ? bp[o] : 0.0;
       const double yn = A.a_base * base + A.b_stage * (y0v + dt * L);
       if (out_lane) op[o] = yn;
-      // one node at a time: interleaving the unrolled WENO evaluations
-      // would exceed the register file
-      __builtin_amdgcn_sched_barrier(0);
+      // a scheduling fence after every HHLB_SCHED_GROUP node-functions:
+      // interleaving more unrolled WENO evaluations exceeds the register file
+      if ((j * NC + fn + 1) % HHLB_SCHED_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
