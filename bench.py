@@ -16,8 +16,14 @@ reports its speed against the FP64 form and its largest moment difference
 from the FP64 form after the same steps (the FP64 form matches the CPU
 oracle to 1e-12).
 
+A second workload rides along in the same JSON line ("batched"): 4096
+independent channels of uneven Nx, Q, Kn, g and wall-temperature ratio, each
+form advancing all of them in one launch per model class and stage, against
+the FP64 form stepping each channel as a solver of its own.
+
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
---forms fp64,mixed_f32,... --no-cpu-baseline.
+--forms fp64,mixed_f32,... --batch-channels C (0 skips the batch)
+--no-cpu-baseline.
 """
 from __future__ import annotations
 
@@ -54,6 +60,88 @@ def bytes_per_node_update(form="fp64", nfun=2):
     writes d2; stage 3 reads hi, lo (2) and d2 and writes hi and lo: 36 bytes
     per function."""
     return nfun * (64 if form == "fp64" else 36)
+
+
+def batch_workload(n_ch=4096, seed=0):
+    """The batched workload: n_ch channels drawn from PCG64(seed) (Nx, Q,
+    log10 Kn, g, T_right/T_left per channel), uniform grid, WENO-5, f and chi,
+    per-channel dt = min(CFL 0.5, Kn/2)."""
+    import paper_1708_03249_amd as H
+    from paper_1708_03249_amd.inputs import batch_draws
+    return [H.Channel(quad=H.HALF_HERMITE, Q=d["Q"], N=d["Q"] - 1, Nx=d["Nx"], adv=H.WENO5,
+                      transverse_dof=2, L=1.0, stretch_A=0.0, Kn=d["Kn"], g=d["g"], T_left=1.0,
+                      T_right=d["T_right"], p0=1.0, dt=-0.5) for d in batch_draws(n_ch, seed)]
+
+
+def run_batch(H, torch, np, args):
+    """Batched workload: every form advances all channels in one launch per
+    class and stage (default launch configuration: direct launches, classes
+    in turn on one stream); compared with the FP64 form stepping each channel
+    as its own solver (timed on a sample of channels)."""
+    chans = batch_workload(args.batch_channels)
+    nu_step = sum(c.V * c.Nx for c in chans)
+    out = {"workload": f"{len(chans)} channels, Nx~U{{64..1024}}, Q~U{{4,8,12}}, log10 Kn~U[-3,1], "
+                       "g~U[-1,0], T_right/T_left~U[1,2] (PCG64 seed 0), uniform grid, WENO5+RK3, "
+                       "f and chi, dt=min(CFL 0.5, Kn/2)",
+           "node_updates_per_step": nu_step, "steps": args.batch_steps, "forms": {}}
+    ref = None
+    for form in ("fp64", "mixed_f32"):
+        s = H.Solver(chans, precision=H.PRECISIONS[form])
+        s.init_equilibrium(1.0, 0.0, 1.0)
+        print(f"[bench] batch {form}: {len(chans)} channels, {args.batch_steps} steps",
+              file=sys.stderr, flush=True)
+        best = s.tuning()   # the default launch configuration
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(args.batch_steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        nw, mass, bad = s.diagnostics()
+        mom = s.moments()
+        torch.cuda.synchronize()
+        assert int(bad.item()) == 0, f"batch {form}: non-finite populations"
+        rec = {"value": nu_step * args.batch_steps / (ms / 1e3), "unit": "node-updates/s",
+               "ms_per_step": ms / args.batch_steps, "tuning": best,
+               "mass_drift": float((mass - 1.0).abs().max().item())}
+        if form == "fp64":
+            ref = mom
+        else:
+            rec["err_vs_fp64"] = moment_diff(np, ref, mom)
+        out["forms"][form] = rec
+        s.close()
+        del mom
+        torch.cuda.empty_cache()
+    # per-instance FP64: one solver (and its own launches) per channel, on an
+    # evenly spaced sample of the channels
+    sample = chans[::max(1, len(chans) // args.instance_sample)][:args.instance_sample]
+    print(f"[bench] per-instance fp64: {len(sample)} solvers x {args.instance_steps} steps",
+          file=sys.stderr, flush=True)
+    solvers = []
+    for c in sample:
+        s = H.Solver([c])
+        s.init_equilibrium(1.0, 0.0, 1.0)
+        s.step(1)
+        solvers.append(s)
+    torch.cuda.synchronize()
+    steps = args.instance_steps
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nu = sum(c.V * c.Nx for c in sample) * steps
+    for s in solvers:
+        s.close()
+    out["per_instance_fp64"] = {"value": nu / el, "unit": "node-updates/s",
+                                "sample": f"{len(sample)} of the channels, one solver each, "
+                                          f"{steps} steps each, launched one after another"}
+    out["batched_vs_per_instance"] = {f: round(r["value"] / out["per_instance_fp64"]["value"], 1)
+                                      for f, r in out["forms"].items()}
+    out["mixed_vs_fp64_batched"] = round(out["forms"]["mixed_f32"]["value"] / out["forms"]["fp64"]["value"], 3)
+    return out
 
 
 def flops_per_node_update(Q=Q, N=Q - 1, nfun=2, nc=8):
@@ -196,6 +284,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed_f32,mixed_bf16,mixed_f16",
                     help="arithmetic forms to time; the first is the primary line")
+    ap.add_argument("--batch-channels", type=int, default=4096,
+                    help="channels of the batched uneven workload (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--instance-sample", type=int, default=64)
+    ap.add_argument("--instance-steps", type=int, default=20)
     ap.add_argument("--cpu-channels", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -262,6 +355,8 @@ def main():
     if "fp64" in results:
         out["speed_vs_fp64"] = {f: round(r["value"] / results["fp64"]["value"], 3)
                                 for f, r in results.items() if f != "fp64"}
+    if args.batch_channels > 0:
+        out["batched"] = run_batch(H, torch, np, args)
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: {args.cpu_channels} channels x {args.cpu_steps} steps",
               file=sys.stderr, flush=True)

@@ -150,6 +150,40 @@ hhlb_status hhlb_init_equilibrium(hhlb_solver *s, double n0, double u0, double T
  * found non-finite populations (it waits for that diagnostics to finish). */
 hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps);
 
+/* Launch configuration of hhlb_step (the arithmetic is the same in every
+ * configuration; results are bit-identical).
+ *  graph_steps:   0 = direct kernel launches on the solver's stream; K > 0 =
+ *                 replay of HIP graphs of K steps (see hhlb_set_graph_steps).
+ *  class_streams: 0 = the model classes (channels sharing quadrature, Q, N,
+ *                 scheme and Dt) advance one after the other on the solver's
+ *                 stream; 1 = with direct launches, each class runs its steps
+ *                 on an internal stream of its own (default priority), forked
+ *                 from and joined back into the solver's stream by events
+ *                 (graph replay always records the one-stream order).
+ *  xcd_map:       1 = consecutive windows of a channel go to the same XCD
+ *                 (the hardware deals blocks round-robin over the 8 XCDs);
+ *                 0 = block b handles window b.
+ *  ms_per_step:   filled in by hhlb_autotune (the measured time). */
+typedef struct {
+  int32_t graph_steps;
+  int32_t class_streams;
+  int32_t xcd_map;
+  float ms_per_step;
+} hhlb_tuning;
+
+/* Set / read the launch configuration (defaults: 0, 0, 1). */
+hhlb_status hhlb_set_tuning(hhlb_solver *s, const hhlb_tuning *t);
+hhlb_status hhlb_get_tuning(const hhlb_solver *s, hhlb_tuning *t);
+
+/* Autotuner: times trial_steps steps of every candidate configuration
+ * (direct launches with class_streams in {0, 1} -- 1 only when there are
+ * several classes -- and graphs of 16 steps, each with xcd_map in {1, 0}) on
+ * the solver's own channels and keeps the fastest; *best_out (may be NULL)
+ * receives it.  The trials advance the state like hhlb_step (candidates x
+ * (trial_steps + 1) steps) and synchronise the stream; call it in place of
+ * warm-up steps. */
+hhlb_status hhlb_autotune(hhlb_solver *s, int32_t trial_steps, hhlb_tuning *best_out);
+
 /* Steps captured per HIP graph (default 0 = direct launches on the solver's
  * stream).  With steps_per_graph > 0, hhlb_step replays graphs of that many
  * steps (and a 1-step graph for the remainder) on an internal stream of

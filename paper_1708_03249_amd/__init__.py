@@ -35,6 +35,15 @@ class HHLBError(RuntimeError):
         self.status = status
 
 
+class _CTuning(ctypes.Structure):
+    _fields_ = [("graph_steps", ctypes.c_int32), ("class_streams", ctypes.c_int32),
+                ("xcd_map", ctypes.c_int32), ("ms_per_step", ctypes.c_float)]
+
+    def as_dict(self):
+        return {"graph_steps": self.graph_steps, "class_streams": self.class_streams,
+                "xcd_map": self.xcd_map, "ms_per_step": self.ms_per_step}
+
+
 class _CChannel(ctypes.Structure):
     _fields_ = [("quad", ctypes.c_int32), ("Q", ctypes.c_int32), ("N", ctypes.c_int32),
                 ("Nx", ctypes.c_int32), ("adv", ctypes.c_int32),
@@ -103,11 +112,15 @@ def lib():
         L.hhlb_launch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.hhlb_destroy.argtypes = [vp]
         L.hhlb_set_graph_steps.argtypes = [vp, i32]
+        L.hhlb_set_tuning.argtypes = [vp, ctypes.POINTER(_CTuning)]
+        L.hhlb_get_tuning.argtypes = [vp, ctypes.POINTER(_CTuning)]
+        L.hhlb_autotune.argtypes = [vp, i32, ctypes.POINTER(_CTuning)]
         for name in ("hhlb_nodes", "hhlb_force_matrix", "hhlb_equilibrium", "hhlb_create",
                      "hhlb_workspace_bytes", "hhlb_bind_workspace", "hhlb_state_offsets",
                      "hhlb_time_steps", "hhlb_set_state", "hhlb_init_equilibrium", "hhlb_step",
                      "hhlb_get_state", "hhlb_moments", "hhlb_diagnostics", "hhlb_launch_info",
-                     "hhlb_destroy", "hhlb_set_graph_steps"):
+                     "hhlb_destroy", "hhlb_set_graph_steps", "hhlb_set_tuning", "hhlb_get_tuning",
+                     "hhlb_autotune"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -199,6 +212,22 @@ class Solver:
 
     def step(self, n_steps: int):
         _check(lib().hhlb_step(self.h, int(n_steps)))
+
+    def set_tuning(self, graph_steps=0, class_streams=0, xcd_map=1):
+        t = _CTuning(int(graph_steps), int(class_streams), int(xcd_map), 0.0)
+        _check(lib().hhlb_set_tuning(self.h, ctypes.byref(t)))
+
+    def tuning(self):
+        t = _CTuning()
+        _check(lib().hhlb_get_tuning(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, trial_steps: int = 10):
+        """Time every launch configuration on these channels and keep the
+        fastest (advances the state like warm-up steps); returns it."""
+        t = _CTuning()
+        _check(lib().hhlb_autotune(self.h, int(trial_steps), ctypes.byref(t)))
+        return t.as_dict()
 
     def set_graph_steps(self, steps_per_graph: int):
         """Steps per replayed HIP graph; 0 = direct launches."""

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -274,8 +275,12 @@ struct hhlb_solver {
   int32_t *flag_host = nullptr;
   hipEvent_t ev_flag = nullptr;
   bool flag_pending = false;
-  // graph replay of the step sequence (0 = direct launches)
-  int graph_steps = 0;   // direct launches: measured no slower than graph replay
+  // launch configuration (hhlb_set_tuning / hhlb_autotune): direct launches,
+  // classes one after the other, XCD-aware window mapping by default
+  hhlb_tuning tuning = {0, 0, 1, 0.0f};
+  std::vector<hipStream_t> cstreams;   // one per model class (class_streams)
+  std::vector<hipEvent_t> cjoin;
+  hipEvent_t cfork = nullptr;
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t gexec_k[2] = {nullptr, nullptr}, gexec_1[2] = {nullptr, nullptr};  // per starting parity
@@ -288,6 +293,9 @@ struct hhlb_solver {
   }
   ~hhlb_solver() {
     drop_graphs();
+    for (hipEvent_t e : cjoin) (void)hipEventDestroy(e);
+    for (hipStream_t st : cstreams) (void)hipStreamDestroy(st);
+    if (cfork) (void)hipEventDestroy(cfork);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (gstream) (void)hipStreamDestroy(gstream);
@@ -441,11 +449,13 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
   }
   // correction ladder (half range): point counts and the |y0| each covers
   const int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
+  double limits[hhlb::kLadder] = {0};
+  if (h.quad == HHLB_HALF_HERMITE) hhlb::correction_limits(r, N, counts, hhlb::kLadder, 3e-16, limits);
   int o = 0;
   for (int j = 0; j < hhlb::kLadder; ++j) {
     d.lad_n[j] = counts[j];
     d.lad_off[j] = o;
-    d.lad_y[j] = h.quad == HHLB_HALF_HERMITE ? hhlb::correction_limit(r, N, counts[j], 3e-16) : 0.0;
+    d.lad_y[j] = limits[j];
     if (counts[j] > 0) {
       std::vector<long double> t2, l2;
       hhlb::gauss_legendre01(counts[j], t2, l2);
@@ -456,6 +466,29 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
     }
     o += counts[j];
   }
+  return HHLB_OK;
+}
+
+// The device tables of a model class, built once per process: the
+// correction-ladder calibration alone takes seconds, and solvers (e.g. one
+// per channel) often repeat the same classes.
+hhlb_status cached_tables(const hhlb_channel &h, int N, int precision, const hhlb::Rule &r, hhlb::DevTables &d) {
+  using Key = std::tuple<int, int, int, double, int>;
+  static std::mutex mu;
+  static std::map<Key, hhlb::DevTables> cache;
+  const Key key{h.quad, h.Q, N, h.p0, precision};
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      d = it->second;
+      return HHLB_OK;
+    }
+  }
+  hhlb_status st = make_tables(h, N, precision, r, d);
+  if (st) return st;
+  std::lock_guard<std::mutex> lock(mu);
+  cache.emplace(key, d);
   return HHLB_OK;
 }
 
@@ -585,7 +618,7 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
           return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) + ": no kernel for quad=" +
                                               std::to_string(h.quad) + " Q=" + std::to_string(h.Q));
         mc.launch = lk->second;
-        st = make_tables(h, N, precision, mc.rule, mc.dev);
+        st = cached_tables(h, N, precision, mc.rule, mc.dev);
         if (st) return st;
         id = (int)s->classes.size();
         s->classes.push_back(std::move(mc));
@@ -826,52 +859,102 @@ hhlb_status hhlb_init_equilibrium(hhlb_solver *s, double n0, double u0, double T
 
 namespace {
 
-// Enqueue one RK stage for every model class.
-void enqueue_stage(hhlb_solver *s, int stage, const void *inf, const void *inc, void *outf, void *outc,
-                   double a_base, double b_stage, hipStream_t stream, const int16_t *lo_in_f = nullptr,
-                   const int16_t *lo_in_c = nullptr, int16_t *lo_out_f = nullptr, int16_t *lo_out_c = nullptr) {
-  for (size_t ci = 0; ci < s->classes.size(); ++ci) {
-    ModelClass &mc = s->classes[ci];
-    hhlb::StageArgs a;
-    a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables) + ci;
-    a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
-    a.wins = (const hhlb::DevWindow *)(s->ws + mc.win_off);
-    a.nwin = (int32_t)mc.windows.size();
-    a.stage = stage;
-    a.inv_dx = (const double *)(s->ws + s->o_invdx);
-    a.gw = (const double *)(s->ws + s->o_gw);
-    a.in_f = inf; a.in_c = inc;
-    a.base_f = s->fA(); a.base_c = s->cA();
-    a.out_f = outf; a.out_c = outc;
-    a.a_base = a_base;
-    a.b_stage = b_stage;
-    a.nwall = (double *)(s->ws + s->o_nwall);
-    a.lo_in_f = lo_in_f; a.lo_in_c = lo_in_c;
-    a.lo_out_f = lo_out_f; a.lo_out_c = lo_out_c;
-    mc.launch(a, stream);
-  }
+// Enqueue one RK stage of model class ci.
+void enqueue_class_stage(hhlb_solver *s, size_t ci, int stage, const void *inf, const void *inc, void *outf,
+                         void *outc, double a_base, double b_stage, hipStream_t stream,
+                         const int16_t *lo_in_f = nullptr, const int16_t *lo_in_c = nullptr,
+                         int16_t *lo_out_f = nullptr, int16_t *lo_out_c = nullptr) {
+  ModelClass &mc = s->classes[ci];
+  hhlb::StageArgs a;
+  a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables) + ci;
+  a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
+  a.wins = (const hhlb::DevWindow *)(s->ws + mc.win_off);
+  a.nwin = (int32_t)mc.windows.size();
+  a.stage = stage;
+  a.xcd_map = s->tuning.xcd_map;
+  a.inv_dx = (const double *)(s->ws + s->o_invdx);
+  a.gw = (const double *)(s->ws + s->o_gw);
+  a.in_f = inf; a.in_c = inc;
+  a.base_f = s->fA(); a.base_c = s->cA();
+  a.out_f = outf; a.out_c = outc;
+  a.a_base = a_base;
+  a.b_stage = b_stage;
+  a.nwall = (double *)(s->ws + s->o_nwall);
+  a.lo_in_f = lo_in_f; a.lo_in_c = lo_in_c;
+  a.lo_out_f = lo_out_f; a.lo_out_c = lo_out_c;
+  mc.launch(a, stream);
 }
 
-// Enqueue n_steps RK-3 steps (Eq. rk3).
+// One RK stage of every class on one stream.
+void enqueue_stage(hhlb_solver *s, int stage, const void *inf, const void *inc, void *outf, void *outc,
+                   double a_base, double b_stage, hipStream_t stream) {
+  for (size_t ci = 0; ci < s->classes.size(); ++ci)
+    enqueue_class_stage(s, ci, stage, inf, inc, outf, outc, a_base, b_stage, stream);
+}
+
+// n_steps RK-3 steps (Eq. rk3) of class ci on one stream, starting from the
+// solver's current state parity (left unchanged).
 //  FP64: stage 1 A -> B, stage 2 B -> C, stage 3 C -> A (pointwise in y^n,
 //        so in place is safe).
 //  Mixed: stage 1 hi -> d1 (B), stage 2 (hi, d1) -> d2 (C), stage 3
 //        (hi, lo, d2) -> the other (hi, lo) copy; the parity then flips.
-void enqueue_steps(hhlb_solver *s, int64_t n_steps, hipStream_t stream) {
+void enqueue_class_steps(hhlb_solver *s, size_t ci, int64_t n_steps, hipStream_t stream) {
+  const int par0 = s->par;
   for (int64_t step = 0; step < n_steps; ++step) {
     if (!s->mixed()) {
-      enqueue_stage(s, 0, s->fA(), s->cA(), s->fB, s->cB, 0.0, 1.0, stream);
-      enqueue_stage(s, 1, s->fB, s->cB, s->fC, s->cC, 0.75, 0.25, stream);
-      enqueue_stage(s, 2, s->fC, s->cC, s->fA(), s->cA(), 1.0 / 3.0, 2.0 / 3.0, stream);
+      enqueue_class_stage(s, ci, 0, s->fA(), s->cA(), s->fB, s->cB, 0.0, 1.0, stream);
+      enqueue_class_stage(s, ci, 1, s->fB, s->cB, s->fC, s->cC, 0.75, 0.25, stream);
+      enqueue_class_stage(s, ci, 2, s->fC, s->cC, s->fA(), s->cA(), 1.0 / 3.0, 2.0 / 3.0, stream);
     } else {
       const int p = s->par, q = p ^ 1;
-      enqueue_stage(s, 0, nullptr, nullptr, s->fB, s->cB, 0.0, 1.0, stream);
-      enqueue_stage(s, 1, s->fB, s->cB, s->fC, s->cC, 0.75, 0.25, stream);
-      enqueue_stage(s, 2, s->fC, s->cC, s->hiF[q], s->hiC[q], 1.0 / 3.0, 2.0 / 3.0, stream, s->loF[p], s->loC[p],
-                    s->loF[q], s->loC[q]);
+      enqueue_class_stage(s, ci, 0, nullptr, nullptr, s->fB, s->cB, 0.0, 1.0, stream);
+      enqueue_class_stage(s, ci, 1, s->fB, s->cB, s->fC, s->cC, 0.75, 0.25, stream);
+      enqueue_class_stage(s, ci, 2, s->fC, s->cC, s->hiF[q], s->hiC[q], 1.0 / 3.0, 2.0 / 3.0, stream,
+                          s->loF[p], s->loC[p], s->loF[q], s->loC[q]);
       s->par = q;
     }
   }
+  s->par = par0;
+}
+
+// n_steps steps of every class.  With one stream the classes run one after
+// the other within each step; with class streams (direct launches only) each
+// class runs its whole step sequence on a stream of its own (classes touch
+// disjoint channels, so nothing orders them), forked from and joined back
+// into `stream` by events.  Graph capture always takes the one-stream form,
+// so the fork/join events are never part of a captured graph.  The state
+// parity advances by n_steps.
+hhlb_status enqueue_steps(hhlb_solver *s, int64_t n_steps, hipStream_t stream, bool capturing = false) {
+  const size_t nc = s->classes.size();
+  if (capturing || !s->tuning.class_streams || nc < 2) {
+    const int par0 = s->par;
+    for (int64_t step = 0; step < n_steps; ++step) {
+      for (size_t ci = 0; ci < nc; ++ci) enqueue_class_steps(s, ci, 1, stream);
+      if (s->mixed()) s->par ^= 1;
+    }
+    if (!s->mixed()) s->par = par0;
+    return HHLB_OK;
+  }
+  if (s->cstreams.size() < nc) {
+    while (s->cstreams.size() < nc) {
+      hipStream_t st;
+      HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      s->cstreams.push_back(st);
+      hipEvent_t ev;
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      s->cjoin.push_back(ev);
+    }
+    if (!s->cfork) HIP_TRY(hipEventCreateWithFlags(&s->cfork, hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventRecord(s->cfork, stream));
+  for (size_t ci = 0; ci < nc; ++ci) {
+    HIP_TRY(hipStreamWaitEvent(s->cstreams[ci], s->cfork, 0));
+    enqueue_class_steps(s, ci, n_steps, s->cstreams[ci]);
+    HIP_TRY(hipEventRecord(s->cjoin[ci], s->cstreams[ci]));
+  }
+  for (size_t ci = 0; ci < nc; ++ci) HIP_TRY(hipStreamWaitEvent(stream, s->cjoin[ci], 0));
+  if (s->mixed() && (n_steps & 1)) s->par ^= 1;
+  return HHLB_OK;
 }
 
 // Capture `steps` steps starting from the current parity (the parity the
@@ -880,9 +963,13 @@ hhlb_status make_graph(hhlb_solver *s, int64_t steps, hipGraphExec_t *out) {
   hipGraph_t g = nullptr;
   const int par0 = s->par;
   HIP_TRY(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal));
-  enqueue_steps(s, steps, s->gstream);
+  hhlb_status st = enqueue_steps(s, steps, s->gstream, true);
   s->par = par0;
   hipError_t e = hipStreamEndCapture(s->gstream, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
   if (e != hipSuccess) return fail(HHLB_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -890,22 +977,10 @@ hhlb_status make_graph(hhlb_solver *s, int64_t steps, hipGraphExec_t *out) {
   return HHLB_OK;
 }
 
-}  // namespace
-
-extern "C" hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
-  if (!s) return fail(HHLB_E_ARG, "null solver");
-  if (n_steps < 0) return fail(HHLB_E_ARG, "n_steps must be >= 0");
-  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
-  if (s->flag_pending) {
-    // the non-finite count of the last hhlb_diagnostics
-    HIP_TRY(hipEventSynchronize(s->ev_flag));
-    s->flag_pending = false;
-    if (*s->flag_host > 0)
-      return fail(HHLB_E_NUMERIC, std::to_string(*s->flag_host) + " non-finite populations in the state");
-  }
-  if (n_steps == 0) return HHLB_OK;
-  if (s->graph_steps <= 0) {
-    enqueue_steps(s, n_steps, s->stream);
+hhlb_status run_steps(hhlb_solver *s, int64_t n_steps) {
+  if (s->tuning.graph_steps <= 0) {
+    hhlb_status st = enqueue_steps(s, n_steps, s->stream);
+    if (st) return st;
     HIP_TRY(hipGetLastError());
     return HHLB_OK;
   }
@@ -916,42 +991,131 @@ extern "C" hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
     HIP_TRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
   }
-  HIP_TRY(hipEventRecord(s->ev_in, s->stream));
-  HIP_TRY(hipStreamWaitEvent(s->gstream, s->ev_in, 0));
-  const int64_t full = n_steps / s->graph_steps, rest = n_steps % s->graph_steps;
+  const int64_t K = s->tuning.graph_steps;
+  const int64_t full = n_steps / K, rest = n_steps % K;
   // the mixed form flips the state parity every step: one graph per
   // starting parity, all captured before the first launch
   for (int p = 0; p < (s->mixed() ? 2 : 1); ++p) {
     const int par0 = s->par;
     s->par = p;
     hhlb_status st = HHLB_OK;
-    if (full && !s->gexec_k[p]) st = make_graph(s, s->graph_steps, &s->gexec_k[p]);
+    if (full && !s->gexec_k[p]) st = make_graph(s, K, &s->gexec_k[p]);
     if (!st && rest && !s->gexec_1[p]) st = make_graph(s, 1, &s->gexec_1[p]);
     s->par = par0;
     if (st) return st;
   }
-  auto launch = [&](int64_t k, hipGraphExec_t *ex) -> hhlb_status {
-    HIP_TRY(hipGraphLaunch(ex[s->par], s->gstream));
-    if (s->mixed() && (k & 1)) s->par ^= 1;
-    return HHLB_OK;
-  };
+  HIP_TRY(hipEventRecord(s->ev_in, s->stream));
+  HIP_TRY(hipStreamWaitEvent(s->gstream, s->ev_in, 0));
   for (int64_t r = 0; r < full; ++r) {
-    hhlb_status st = launch(s->graph_steps, s->gexec_k);
-    if (st) return st;
+    HIP_TRY(hipGraphLaunch(s->gexec_k[s->par], s->gstream));
+    if (s->mixed() && (K & 1)) s->par ^= 1;
   }
   for (int64_t r = 0; r < rest; ++r) {
-    hhlb_status st = launch(1, s->gexec_1);
-    if (st) return st;
+    HIP_TRY(hipGraphLaunch(s->gexec_1[s->par], s->gstream));
+    if (s->mixed()) s->par ^= 1;
   }
   HIP_TRY(hipEventRecord(s->ev_out, s->gstream));
   HIP_TRY(hipStreamWaitEvent(s->stream, s->ev_out, 0));
   return HHLB_OK;
 }
 
+hhlb_status check_flag(hhlb_solver *s) {
+  if (s->flag_pending) {
+    // the non-finite count of the last hhlb_diagnostics
+    HIP_TRY(hipEventSynchronize(s->ev_flag));
+    s->flag_pending = false;
+    if (*s->flag_host > 0)
+      return fail(HHLB_E_NUMERIC, std::to_string(*s->flag_host) + " non-finite populations in the state");
+  }
+  return HHLB_OK;
+}
+
+}  // namespace
+
+extern "C" hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps) {
+  if (!s) return fail(HHLB_E_ARG, "null solver");
+  if (n_steps < 0) return fail(HHLB_E_ARG, "n_steps must be >= 0");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  hhlb_status st = check_flag(s);
+  if (st) return st;
+  if (n_steps == 0) return HHLB_OK;
+  return run_steps(s, n_steps);
+}
+
 extern "C" hhlb_status hhlb_set_graph_steps(hhlb_solver *s, int32_t steps_per_graph) {
   if (!s || steps_per_graph < 0) return fail(HHLB_E_ARG, "need a solver and steps_per_graph >= 0");
   s->drop_graphs();
-  s->graph_steps = steps_per_graph;
+  s->tuning.graph_steps = steps_per_graph;
+  return HHLB_OK;
+}
+
+extern "C" hhlb_status hhlb_set_tuning(hhlb_solver *s, const hhlb_tuning *t) {
+  if (!s || !t) return fail(HHLB_E_ARG, "null argument");
+  if (t->graph_steps < 0 || (t->class_streams != 0 && t->class_streams != 1) || (t->xcd_map != 0 && t->xcd_map != 1))
+    return fail(HHLB_E_ARG, "graph_steps >= 0, class_streams and xcd_map 0 or 1");
+  s->drop_graphs();
+  s->tuning.graph_steps = t->graph_steps;
+  s->tuning.class_streams = t->class_streams;
+  s->tuning.xcd_map = t->xcd_map;
+  return HHLB_OK;
+}
+
+extern "C" hhlb_status hhlb_get_tuning(const hhlb_solver *s, hhlb_tuning *t) {
+  if (!s || !t) return fail(HHLB_E_ARG, "null argument");
+  *t = s->tuning;
+  return HHLB_OK;
+}
+
+extern "C" hhlb_status hhlb_autotune(hhlb_solver *s, int32_t trial_steps, hhlb_tuning *best_out) {
+  if (!s || trial_steps < 1) return fail(HHLB_E_ARG, "need a solver and trial_steps >= 1");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  hhlb_status st = check_flag(s);
+  if (st) return st;
+  const bool multi = s->classes.size() > 1;
+  std::vector<hhlb_tuning> cands;
+  for (int gs : {0, 16})
+    for (int cs : {0, 1})
+      for (int xm : {1, 0}) {
+        if (cs && (!multi || gs > 0)) continue;   // class streams apply to direct launches
+        hhlb_tuning t{};
+        t.graph_steps = gs;
+        t.class_streams = cs;
+        t.xcd_map = xm;
+        cands.push_back(t);
+      }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const hhlb_tuning saved = s->tuning;
+  hhlb_tuning best = saved;
+  float best_ms = 0.0f;
+  bool have = false;
+  for (hhlb_tuning &t : cands) {
+    s->drop_graphs();
+    s->tuning = t;
+    // one untimed step builds graphs and streams, then the timed trial
+    st = run_steps(s, 1);
+    if (st) break;
+    hipError_t e = hipEventRecord(e0, s->stream);
+    if (e == hipSuccess) st = run_steps(s, trial_steps);
+    if (!st && e == hipSuccess) e = hipEventRecord(e1, s->stream);
+    if (!st && e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (!st && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) st = fail(HHLB_E_HIP, std::string("autotune timing: ") + hipGetErrorString(e));
+    if (st) break;
+    t.ms_per_step = ms / trial_steps;
+    if (!have || t.ms_per_step < best_ms) { best = t; best_ms = t.ms_per_step; have = true; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->drop_graphs();
+  if (st) {
+    s->tuning = saved;
+    return st;
+  }
+  s->tuning = best;
+  if (best_out) *best_out = best;
   return HHLB_OK;
 }
 

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
   __shared__ double s_T[kMfmaEq ? 2 * 64 * 17 : (kMfmaK ? 64 * 17 : 1)];
   const int hw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int w = xcd_window(blockIdx.x, A.nwin);
+  const int w = A.xcd_map ? xcd_window(blockIdx.x, A.nwin) : (int)blockIdx.x;
   const DevWindow win = wins[w];
   const DevChannel C = chans[win.ch];
   const int Nx = C.Nx;

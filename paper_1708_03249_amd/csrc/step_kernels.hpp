@@ -113,6 +113,7 @@ struct StageArgs {
   const DevWindow *wins;
   int32_t nwin;
   int32_t stage;             // 0, 1, 2 (only stage 2 writes the wall densities)
+  int32_t xcd_map;           // 1: XCD-aware block -> window mapping, 0: identity
   const double *inv_dx;      // per cell
   const double *gw;          // wall equilibria
   // state arrays: double (FP64 form) or float (mixed form)
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs A) {
   constexpr int V = QUAD == 0 ? 2 * Q : Q;
   constexpr int H = V / 2;
   constexpr int NC = NFUN;
-  const int w = xcd_window(blockIdx.x, A.nwin);
+  const int w = A.xcd_map ? xcd_window(blockIdx.x, A.nwin) : (int)blockIdx.x;
   const DevWindow win = A.wins[w];
   const DevChannel C = A.chans[win.ch];
   const DevTables *__restrict__ tb = A.tb;
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
   __shared__ double s_T[kMfma ? 2 * 64 * 17 : 1];
   const int hw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int w = xcd_window(blockIdx.x, A.nwin);
+  const int w = A.xcd_map ? xcd_window(blockIdx.x, A.nwin) : (int)blockIdx.x;
   const DevWindow win = wins[w];
   const DevChannel C = chans[win.ch];
   const int Nx = C.Nx;

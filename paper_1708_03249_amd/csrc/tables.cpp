@@ -346,31 +346,47 @@ void equilibrium(const Rule &r, int N, ld u, ld T, double *g) {
 }
 
 double correction_limit(const Rule &r, int N, int nc, double tol) {
-  if (r.quad != kHalf || nc <= 0) return 0.0;
+  double out = 0.0;
+  correction_limits(r, N, &nc, 1, tol, &out);
+  return out;
+}
+
+void correction_limits(const Rule &r, int N, const int *ncs, int n, double tol, double *out) {
+  for (int j = 0; j < n; ++j) out[j] = 0.0;
+  if (r.quad != kHalf) return;
   const ld Ts[4] = {0.5L, 1.0L, 2.0L, 3.0L};
   std::vector<ld> g(r.V), gr(r.V);
-  double best = 0.0;
-  for (int e = 0; e <= 96; ++e) {
-    ld y = 1e-6L * powl(10.0L, e / 16.0L);   // 1e-6 .. 1
-    bool ok = true;
-    for (ld T : Ts) {
-      for (int sgn = -1; sgn <= 1 && ok; sgn += 2) {
-        ld u = sgn * y * sqrtl(T);
-        equilibrium_nc(r, N, u, T, nc, g.data());
-        equilibrium_nc(r, N, u, T, 40, gr.data());
-        ld mx = 0, err = 0;
-        for (int k = 0; k < r.V; ++k) {
-          mx = std::max(mx, fabsl(gr[k]));
-          err = std::max(err, fabsl(g[k] - gr[k]));
-        }
-        if (err > tol * mx) ok = false;
-      }
-      if (!ok) break;
-    }
-    if (!ok) break;
-    best = (double)y;
+  std::vector<bool> active(n);
+  int n_active = 0;
+  for (int j = 0; j < n; ++j) {
+    active[j] = ncs[j] > 0;
+    n_active += active[j];
   }
-  return best;
+  // the grid 1e-6 .. 1 of |y0|; a count keeps the last y0 of an unbroken run
+  // of passes; the 40-point reference is shared by every count
+  for (int e = 0; e <= 96 && n_active > 0; ++e) {
+    const ld y = 1e-6L * powl(10.0L, e / 16.0L);
+    std::vector<bool> ok(n, true);
+    for (ld T : Ts)
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const ld u = sgn * y * sqrtl(T);
+        equilibrium_nc(r, N, u, T, 40, gr.data());
+        ld mx = 0;
+        for (int k = 0; k < r.V; ++k) mx = std::max(mx, fabsl(gr[k]));
+        for (int j = 0; j < n; ++j) {
+          if (!active[j] || !ok[j]) continue;
+          equilibrium_nc(r, N, u, T, ncs[j], g.data());
+          ld err = 0;
+          for (int k = 0; k < r.V; ++k) err = std::max(err, fabsl(g[k] - gr[k]));
+          if (err > tol * mx) ok[j] = false;
+        }
+      }
+    for (int j = 0; j < n; ++j) {
+      if (!active[j]) continue;
+      if (ok[j]) out[j] = (double)y;
+      else { active[j] = false; --n_active; }
+    }
+  }
 }
 
 }  // namespace hhlb

@@ -38,6 +38,8 @@ void equilibrium_nc(const Rule &r, int N, long double u, long double T, int nc, 
 // Largest |y0| = |u| sqrt(m/T) for which nc correction points keep the
 // half-range equilibrium within tol of max|g| (T in [0.5, 3]).
 double correction_limit(const Rule &r, int N, int nc, double tol);
+// The same for n point counts at once (out[j] for ncs[j]; 0 for ncs[j] <= 0).
+void correction_limits(const Rule &r, int N, const int *ncs, int n, double tol, double *out);
 
 // Gauss-Legendre nodes tau_i in (0,1) and weights lam_i (sum 1), n points.
 void gauss_legendre01(int n, std::vector<long double> &tau, std::vector<long double> &lam);
