@@ -144,6 +144,60 @@ def run_batch(H, torch, np, args):
     return out
 
 
+def steady_workload():
+    """The steady-state study: HHLB(7;8) and the full-range HLB(15;16), both
+    V = 16, on Nx = 512 cells stretched towards the walls (A = 0.9), WENO-5,
+    T_left = 1, T_right = 2, g = -0.5, Kn in {0.01, 0.1, 1}, CFL 0.5."""
+    import paper_1708_03249_amd as H
+    return [H.Channel(quad=quad, Q=Q, N=Q - 1, Nx=512, adv=H.WENO5, transverse_dof=2, L=1.0,
+                      stretch_A=0.9, Kn=kn, g=-0.5, T_left=1.0, T_right=2.0, p0=1.0, dt=-0.5)
+            for quad, Q in ((H.HALF_HERMITE, 8), (H.FULL_HERMITE, 16)) for kn in (0.01, 0.1, 1.0)]
+
+
+def run_steady(H, torch, np, args):
+    """Advance the steady-state study (all six channels in one solver) until
+    every channel's residual is below args.residual (checked every
+    args.check_every steps), reporting the steps taken and the steady flow."""
+    chans = steady_workload()
+    s = H.Solver(chans)
+    s.init_equilibrium(1.0, 0.0, 1.0)
+    done, t0, res = 0, time.perf_counter(), None
+    conv = [None] * len(chans)
+    while done < args.max_steps:
+        s.step(args.check_every)
+        done += args.check_every
+        _, _, bad, r = s.diagnostics(residual=True)
+        r = r.cpu().numpy()
+        if int(bad.item()):
+            raise RuntimeError("steady study: non-finite populations")
+        for k in range(len(chans)):
+            if conv[k] is None and r[k] <= args.residual:
+                conv[k] = done
+        if done % (20 * args.check_every) == 0:
+            print(f"[steady] {done} steps, residuals {' '.join(f'{x:.1e}' for x in r)}",
+                  file=sys.stderr, flush=True)
+        res = r
+        if all(c is not None for c in conv):
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n, u, T = (x.cpu().numpy() for x in s.moments())
+    nw, mass, _ = s.diagnostics()
+    nw, mass = nw.cpu().numpy(), mass.cpu().numpy()
+    rows = []
+    for k, ch in enumerate(chans):
+        a, b = s.cells[k], s.cells[k + 1]
+        rows.append({"model": ("HHLB" if ch.quad == H.HALF_HERMITE else "HLB") + f"({ch.N};{ch.Q})",
+                     "Kn": ch.Kn, "steps_to_residual": conv[k], "residual": float(res[k]),
+                     "dt": float(s.dt[k]), "max_abs_u": float(np.abs(u[a:b]).max()),
+                     "n_left": float(n[a]), "n_right": float(n[b - 1]),
+                     "T_left_cell": float(T[a]), "T_right_cell": float(T[b - 1]),
+                     "n_wall": [float(x) for x in nw[k]], "mass": float(mass[k])})
+    s.close()
+    return {"workload": steady_workload.__doc__.split("\n\n")[0].replace("\n", " ").strip(),
+            "residual_target": args.residual, "steps": done, "wall_s": round(wall, 1), "channels": rows}
+
+
 def flops_per_node_update(Q=Q, N=Q - 1, nfun=2, nc=8):
     """Algorithmic floating-point operations of one node-update (both
     functions, three stages), counting an FMA as two: WENO-5 face value
@@ -289,6 +343,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--instance-sample", type=int, default=64)
     ap.add_argument("--instance-steps", type=int, default=20)
+    ap.add_argument("--steady", action="store_true",
+                    help="only run the steady-state study to --residual")
+    ap.add_argument("--residual", type=float, default=1e-10)
+    ap.add_argument("--check-every", type=int, default=1000)
+    ap.add_argument("--max-steps", type=int, default=3_000_000)
     ap.add_argument("--cpu-channels", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -304,6 +363,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": n * 8, "copies": 3}))
+        return
+    if args.steady:
+        import numpy as np
+        import torch
+        import paper_1708_03249_amd as H
+        print(json.dumps({"steady": run_steady(H, torch, np, args)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "

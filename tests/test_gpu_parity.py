@@ -289,3 +289,32 @@ def test_launch_configurations_bit_identical(form):
     assert np.array_equal(c.cpu().numpy(), cr.cpu().numpy())
     s.close()
     r.close()
+
+
+@pytest.mark.parametrize("form,tol", [("fp64", 1e-10), ("mixed_f32", 1e-4)])
+def test_residual_against_oracle_rhs(form, tol):
+    """The residual diagnostic, ||L[y]||_inf / ||y||_inf over f and chi (the
+    larger of the two), against the same quantity from the oracle's
+    right-hand side on the state the GPU holds."""
+    import torch
+    import oracle as O
+    from gpu_common import to_oracle
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=8, Nx=120, adv=h.WENO5, stretch_A=0.9, T_left=1.0,
+                       T_right=2.0, g=-0.5, Kn=kn, dt=-0.5) for kn in (0.01, 1.0)]
+    states = initial_states(chans, seed=21, perturb=0.05)
+    s = h.Solver(chans, precision=h.PRECISIONS[form])
+    s.set_state(torch.from_numpy(np.concatenate([st[0].ravel() for st in states])).cuda(),
+                torch.from_numpy(np.concatenate([st[1].ravel() for st in states])).cuda())
+    s.step(20)
+    f, c = s.get_state()
+    nw, mass, bad, res = s.diagnostics(residual=True)
+    torch.cuda.synchronize()
+    f, c, res = f.cpu().numpy(), c.cpu().numpy(), res.cpu().numpy()
+    for k, ch in enumerate(chans):
+        fk = s.channel_view(torch.from_numpy(f), k).numpy()
+        ck = s.channel_view(torch.from_numpy(c), k).numpy()
+        Lf, Lc, _ = O.rhs(to_oracle(ch, dt=float(s.dt[k])), fk, ck)
+        r = max(np.abs(Lf).max() / np.abs(fk).max(), np.abs(Lc).max() / np.abs(ck).max())
+        assert abs(res[k] / r - 1) < tol, (form, k, res[k], r)
+    s.close()
