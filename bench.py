@@ -268,6 +268,7 @@ def run_form(H, torch, np, chans, form, args):
     """Warm up, time args.steps steps of one arithmetic form; return its
     record and the final moments (device tensors)."""
     s = H.Solver(chans, precision=H.PRECISIONS[form])
+    s.set_tuning(waves_per_window=args.waves_per_window)
     s.init_equilibrium(1.0, 0.0, 1.0)
     print(f"[bench] {form}: {len(chans)} channels x Nx={NX}, V={2 * Q}; workspace "
           f"{s.ws_bytes / 2**30:.2f} GiB; warmup {args.warmup}", file=sys.stderr, flush=True)
@@ -338,6 +339,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed_f32,mixed_bf16,mixed_f16",
                     help="arithmetic forms to time; the first is the primary line")
+    ap.add_argument("--waves-per-window", type=int, default=2, choices=(2, 4),
+                    help="stage-kernel shape for the large workload (4: FP64 four-wave kernel)")
     ap.add_argument("--batch-channels", type=int, default=4096,
                     help="channels of the batched uneven workload (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=1000)

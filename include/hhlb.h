@@ -163,22 +163,27 @@ hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps);
  *  xcd_map:       1 = consecutive windows of a channel go to the same XCD
  *                 (the hardware deals blocks round-robin over the 8 XCDs);
  *                 0 = block b handles window b.
+ *  waves_per_window: 2 = one wave per momentum half holds both f and chi of
+ *                 a 64-cell window; 4 = one wave per half and function (FP64
+ *                 half-range channels with chi; other classes keep 2).
  *  ms_per_step:   filled in by hhlb_autotune (the measured time). */
 typedef struct {
   int32_t graph_steps;
   int32_t class_streams;
   int32_t xcd_map;
+  int32_t waves_per_window;
   float ms_per_step;
 } hhlb_tuning;
 
-/* Set / read the launch configuration (defaults: 0, 0, 1). */
+/* Set / read the launch configuration (defaults: 0, 0, 1, 2). */
 hhlb_status hhlb_set_tuning(hhlb_solver *s, const hhlb_tuning *t);
 hhlb_status hhlb_get_tuning(const hhlb_solver *s, hhlb_tuning *t);
 
 /* Autotuner: times trial_steps steps of every candidate configuration
- * (direct launches with class_streams in {0, 1} -- 1 only when there are
- * several classes -- and graphs of 16 steps, each with xcd_map in {1, 0}) on
- * the solver's own channels and keeps the fastest; *best_out (may be NULL)
+ * (waves_per_window in {2, 4} when a class has the four-wave kernel; direct
+ * launches with class_streams in {0, 1} -- 1 only when there are several
+ * classes -- and graphs of 16 steps; each with xcd_map in {1, 0}) on the
+ * solver's own channels and keeps the fastest; *best_out (may be NULL)
  * receives it.  The trials advance the state like hhlb_step (candidates x
  * (trial_steps + 1) steps) and synchronise the stream; call it in place of
  * warm-up steps. */

@@ -37,11 +37,13 @@ class HHLBError(RuntimeError):
 
 class _CTuning(ctypes.Structure):
     _fields_ = [("graph_steps", ctypes.c_int32), ("class_streams", ctypes.c_int32),
-                ("xcd_map", ctypes.c_int32), ("ms_per_step", ctypes.c_float)]
+                ("xcd_map", ctypes.c_int32), ("waves_per_window", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_float)]
 
     def as_dict(self):
         return {"graph_steps": self.graph_steps, "class_streams": self.class_streams,
-                "xcd_map": self.xcd_map, "ms_per_step": self.ms_per_step}
+                "xcd_map": self.xcd_map, "waves_per_window": self.waves_per_window,
+                "ms_per_step": self.ms_per_step}
 
 
 class _CChannel(ctypes.Structure):
@@ -213,8 +215,8 @@ class Solver:
     def step(self, n_steps: int):
         _check(lib().hhlb_step(self.h, int(n_steps)))
 
-    def set_tuning(self, graph_steps=0, class_streams=0, xcd_map=1):
-        t = _CTuning(int(graph_steps), int(class_streams), int(xcd_map), 0.0)
+    def set_tuning(self, graph_steps=0, class_streams=0, xcd_map=1, waves_per_window=2):
+        t = _CTuning(int(graph_steps), int(class_streams), int(xcd_map), int(waves_per_window), 0.0)
         _check(lib().hhlb_set_tuning(self.h, ctypes.byref(t)))
 
     def tuning(self):

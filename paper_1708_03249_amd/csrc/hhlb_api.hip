@@ -236,7 +236,8 @@ struct ModelClass {
   double p0;
   hhlb::Rule rule;
   hhlb::DevTables dev;
-  Launcher launch = nullptr;
+  Launcher launch = nullptr;    // two waves per window
+  Launcher launch4 = nullptr;   // four waves per window (FP64, f and chi), if built
   std::vector<hhlb::DevWindow> windows;
   size_t win_off = 0;  // byte offset in workspace
 };
@@ -277,7 +278,7 @@ struct hhlb_solver {
   bool flag_pending = false;
   // launch configuration (hhlb_set_tuning / hhlb_autotune): direct launches,
   // classes one after the other, XCD-aware window mapping by default
-  hhlb_tuning tuning = {0, 0, 1, 0.0f};
+  hhlb_tuning tuning = {0, 0, 1, 2, 0.0f};
   std::vector<hipStream_t> cstreams;   // one per model class (class_streams)
   std::vector<hipEvent_t> cjoin;
   hipEvent_t cfork = nullptr;
@@ -613,11 +614,14 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
         std::string err;
         int st = hhlb::build_rule(h.quad, h.Q, h.p0, mc.rule, err);
         if (st) return fail(st, "channel " + std::to_string(c) + ": " + err);
-        auto lk = launchers().find({h.quad, h.Q, h.transverse_dof > 0 ? 2 : 1, h.adv, precision});
+        const int nf = h.transverse_dof > 0 ? 2 : 1;
+        auto lk = launchers().find({h.quad, h.Q, nf, h.adv, precision, 2});
         if (lk == launchers().end())
           return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) + ": no kernel for quad=" +
                                               std::to_string(h.quad) + " Q=" + std::to_string(h.Q));
         mc.launch = lk->second;
+        auto lk4 = launchers().find({h.quad, h.Q, nf, h.adv, precision, 4});
+        if (lk4 != launchers().end()) mc.launch4 = lk4->second;
         st = cached_tables(h, N, precision, mc.rule, mc.dev);
         if (st) return st;
         id = (int)s->classes.size();
@@ -882,7 +886,7 @@ void enqueue_class_stage(hhlb_solver *s, size_t ci, int stage, const void *inf, 
   a.nwall = (double *)(s->ws + s->o_nwall);
   a.lo_in_f = lo_in_f; a.lo_in_c = lo_in_c;
   a.lo_out_f = lo_out_f; a.lo_out_c = lo_out_c;
-  mc.launch(a, stream);
+  (s->tuning.waves_per_window == 4 && mc.launch4 ? mc.launch4 : mc.launch)(a, stream);
 }
 
 // One RK stage of every class on one stream.
@@ -1051,12 +1055,14 @@ extern "C" hhlb_status hhlb_set_graph_steps(hhlb_solver *s, int32_t steps_per_gr
 
 extern "C" hhlb_status hhlb_set_tuning(hhlb_solver *s, const hhlb_tuning *t) {
   if (!s || !t) return fail(HHLB_E_ARG, "null argument");
-  if (t->graph_steps < 0 || (t->class_streams != 0 && t->class_streams != 1) || (t->xcd_map != 0 && t->xcd_map != 1))
-    return fail(HHLB_E_ARG, "graph_steps >= 0, class_streams and xcd_map 0 or 1");
+  if (t->graph_steps < 0 || (t->class_streams != 0 && t->class_streams != 1) || (t->xcd_map != 0 && t->xcd_map != 1) ||
+      (t->waves_per_window != 2 && t->waves_per_window != 4))
+    return fail(HHLB_E_ARG, "graph_steps >= 0, class_streams and xcd_map 0 or 1, waves_per_window 2 or 4");
   s->drop_graphs();
   s->tuning.graph_steps = t->graph_steps;
   s->tuning.class_streams = t->class_streams;
   s->tuning.xcd_map = t->xcd_map;
+  s->tuning.waves_per_window = t->waves_per_window;
   return HHLB_OK;
 }
 
@@ -1072,17 +1078,22 @@ extern "C" hhlb_status hhlb_autotune(hhlb_solver *s, int32_t trial_steps, hhlb_t
   hhlb_status st = check_flag(s);
   if (st) return st;
   const bool multi = s->classes.size() > 1;
+  bool has4 = false;
+  for (auto &mc : s->classes) has4 = has4 || mc.launch4 != nullptr;
   std::vector<hhlb_tuning> cands;
-  for (int gs : {0, 16})
-    for (int cs : {0, 1})
-      for (int xm : {1, 0}) {
-        if (cs && (!multi || gs > 0)) continue;   // class streams apply to direct launches
-        hhlb_tuning t{};
-        t.graph_steps = gs;
-        t.class_streams = cs;
-        t.xcd_map = xm;
-        cands.push_back(t);
-      }
+  for (int wpw : {2, 4})
+    for (int gs : {0, 16})
+      for (int cs : {0, 1})
+        for (int xm : {1, 0}) {
+          if (cs && (!multi || gs > 0)) continue;   // class streams apply to direct launches
+          if (wpw == 4 && !has4) continue;
+          hhlb_tuning t{};
+          t.graph_steps = gs;
+          t.class_streams = cs;
+          t.xcd_map = xm;
+          t.waves_per_window = wpw;
+          cands.push_back(t);
+        }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));

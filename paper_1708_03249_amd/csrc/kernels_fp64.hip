@@ -13,12 +13,22 @@ void launch_stage(const StageArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((stage_kernel<QUAD, Q, NF, ADV>), dim3(a.nwin), dim3(64), 0, s, a);
 }
 
+template <int Q, int ADV>
+void launch_quarter(const StageArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((stage_kernel_quarter<Q, ADV>), dim3(a.nwin), dim3(256), 0, s, a, a.tb, a.chans, a.wins,
+                     a.inv_dx, a.gw, (const double *)a.in_f, (const double *)a.in_c);
+}
+
 template <int QUAD, int Q>
 void add(LaunchMap &m) {
-  m[{QUAD, Q, 1, 0, 0}] = launch_stage<QUAD, Q, 1, 0>;
-  m[{QUAD, Q, 1, 1, 0}] = launch_stage<QUAD, Q, 1, 1>;
-  m[{QUAD, Q, 2, 0, 0}] = launch_stage<QUAD, Q, 2, 0>;
-  m[{QUAD, Q, 2, 1, 0}] = launch_stage<QUAD, Q, 2, 1>;
+  m[{QUAD, Q, 1, 0, 0, 2}] = launch_stage<QUAD, Q, 1, 0>;
+  m[{QUAD, Q, 1, 1, 0, 2}] = launch_stage<QUAD, Q, 1, 1>;
+  m[{QUAD, Q, 2, 0, 0, 2}] = launch_stage<QUAD, Q, 2, 0>;
+  m[{QUAD, Q, 2, 1, 0, 2}] = launch_stage<QUAD, Q, 2, 1>;
+  if constexpr (QUAD == 0) {   // four waves per window: f and chi, half range
+    m[{QUAD, Q, 2, 0, 0, 4}] = launch_quarter<Q, 0>;
+    m[{QUAD, Q, 2, 1, 0, 4}] = launch_quarter<Q, 1>;
+  }
 }
 
 }  // namespace

@@ -14,10 +14,10 @@ void launch_stage(const StageArgs &a, hipStream_t s) {
 
 template <int Q>
 void add(LaunchMap &m) {
-  m[{0, Q, 1, 0, kPrecF32}] = launch_stage<Q, 1, 0>;
-  m[{0, Q, 1, 1, kPrecF32}] = launch_stage<Q, 1, 1>;
-  m[{0, Q, 2, 0, kPrecF32}] = launch_stage<Q, 2, 0>;
-  m[{0, Q, 2, 1, kPrecF32}] = launch_stage<Q, 2, 1>;
+  m[{0, Q, 1, 0, kPrecF32, 2}] = launch_stage<Q, 1, 0>;
+  m[{0, Q, 1, 1, kPrecF32, 2}] = launch_stage<Q, 1, 1>;
+  m[{0, Q, 2, 0, kPrecF32, 2}] = launch_stage<Q, 2, 0>;
+  m[{0, Q, 2, 1, kPrecF32, 2}] = launch_stage<Q, 2, 1>;
 }
 
 }  // namespace

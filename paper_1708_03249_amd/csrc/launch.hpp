@@ -11,8 +11,9 @@
 namespace hhlb {
 
 using Launcher = void (*)(const StageArgs &, hipStream_t);
-// (quadrature kind, Q, functions (1 = f, 2 = f and chi), advection, precision)
-using LaunchKey = std::tuple<int, int, int, int, int>;
+// (quadrature kind, Q, functions (1 = f, 2 = f and chi), advection, precision,
+//  waves per window: 2 = the two-wave kernels, 4 = the four-wave FP64 kernel)
+using LaunchKey = std::tuple<int, int, int, int, int, int>;
 using LaunchMap = std::map<LaunchKey, Launcher>;
 
 void register_fp64(LaunchMap &m);

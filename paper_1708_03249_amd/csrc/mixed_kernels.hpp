@@ -68,14 +68,16 @@ __device__ __forceinline__ float weno5f(float a, float b, float c, float d, floa
   const float r1 = ldexpf(s1, -ex), r2 = ldexpf(s2, -ex), r3 = ldexpf(s3, -ex);
   const float q1s = r1 * r1, q2s = r2 * r2, q3s = r3 * r3;
   const float p1 = 0.1f * q2s * q3s, p2 = 0.6f * q1s * q3s, p3 = 0.3f * q1s * q2s;
-  const float den = p1 + p2 + p3;
-  const float tiny = 1e-17f;
-  const float z1 = q1s < tiny ? 0.1f : 0.0f, z2 = q2s < tiny ? 0.6f : 0.0f, z3 = q3s < tiny ? 0.3f : 0.0f;
-  const bool regular = den > 1e-37f;
-  const float n1 = regular ? p1 : z1, n2 = regular ? p2 : z2, n3 = regular ? p3 : z3;
+  float n1 = p1, n2 = p2, n3 = p3, dd = p1 + p2 + p3;
+  if (!(dd > 1e-37f)) {   // limit rule, as in the FP64 form
+    const float tiny = 1e-17f;
+    n1 = q1s < tiny ? 0.1f : 0.0f;
+    n2 = q2s < tiny ? 0.6f : 0.0f;
+    n3 = q3s < tiny ? 0.3f : 0.0f;
+    dd = n1 + n2 + n3;
+  }
   // 1/6 of the candidate stencils folded into the normalisation
-  const float inv = __builtin_amdgcn_rcpf(6.0f * (regular ? den : z1 + z2 + z3));
-  return (n1 * F1 + n2 * F2 + n3 * F3) * inv;
+  return (n1 * F1 + n2 * F2 + n3 * F3) * __builtin_amdgcn_rcpf(6.0f * dd);
 }
 
 // Correction word of y = hi + lo: lo counts 2^-15 ulps of hi (|lo| <= 2^14).

@@ -27,6 +27,9 @@ constexpr int kWin = 58;       // output cells per wavefront
 #ifndef HHLB_HALF_WAVES
 #define HHLB_HALF_WAVES 3
 #endif
+#ifndef HHLB_QUARTER_WAVES
+#define HHLB_QUARTER_WAVES 4
+#endif
 // node-functions per scheduling section in the advection pass
 #ifndef HHLB_SCHED_GROUP
 #define HHLB_SCHED_GROUP 1
@@ -188,14 +191,18 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
   const double r1 = ldexp(s1, -ex), r2 = ldexp(s2, -ex), r3 = ldexp(s3, -ex);
   const double q1s = r1 * r1, q2s = r2 * r2, q3s = r3 * r3;
   const double p1 = 0.1 * q2s * q3s, p2 = 0.6 * q1s * q3s, p3 = 0.3 * q1s * q2s;
-  const double den = p1 + p2 + p3;
-  // limit of Table (weno): ideal weights restricted to the vanishing sigmas
-  const double tiny = 1e-125;
-  const double z1 = q1s < tiny ? 0.1 : 0.0, z2 = q2s < tiny ? 0.6 : 0.0, z3 = q3s < tiny ? 0.3 : 0.0;
-  const bool regular = den > 1e-250;
-  const double n1 = regular ? p1 : z1, n2 = regular ? p2 : z2, n3 = regular ? p3 : z3;
-  const double inv = recip(regular ? den : z1 + z2 + z3);
-  return (n1 * F1 + n2 * F2 + n3 * F3) * inv;
+  double n1 = p1, n2 = p2, n3 = p3, dd = p1 + p2 + p3;
+  if (!(dd > 1e-250)) {
+    // limit of Table (weno): ideal weights restricted to the vanishing
+    // sigmas (a branch no lane takes in smooth flow, so the common path
+    // carries no selects)
+    const double tiny = 1e-125;
+    n1 = q1s < tiny ? 0.1 : 0.0;
+    n2 = q2s < tiny ? 0.6 : 0.0;
+    n3 = q3s < tiny ? 0.3 : 0.0;
+    dd = n1 + n2 + n3;
+  }
+  return (n1 * F1 + n2 * F2 + n3 * F3) * recip(dd);
 }
 
 // Third-order upwind-biased face value (-f_{i-1} + 5 f_i + 2 f_{i+1})/6.
@@ -782,6 +789,267 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
       // interleaving more unrolled WENO evaluations exceeds the register file
       if ((j * NC + fn + 1) % HHLB_SCHED_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
     }
+  }
+}
+
+// The contraction of mfma_contract16 through an unpadded 64 x 16 tile whose
+// columns are XOR-swizzled by the row (column c of row r at c ^ (r & 15)):
+// the row writes, the B-operand reads and the D writes then spread over the
+// LDS banks as with the padded tile, in 8 KB instead of 8.5 KB per wave.
+__device__ __forceinline__ void mfma_contract16_sw(const double aM[4], const double X[16], double OUT[16],
+                                                   double *T, int lane) {
+  const int sw = lane & 15;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) T[lane * 16 + (k ^ sw)] = X[k];
+  __builtin_amdgcn_wave_barrier();
+  dbl4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    acc[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const double *row = T + (16 * cb + sw) * 16;   // row r = 16 cb + (lane & 15): r & 15 = sw
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const double b = row[(4 * kc + (lane >> 4)) ^ sw];
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aM[kc], b, acc[cb], 0, 0, 0);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[(16 * cb + sw) * 16 + ((4 * r + (lane >> 4)) ^ sw)] = acc[cb][r];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) OUT[k] = T[lane * 16 + (k ^ sw)];
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Half-range kernel with four waves per window: wave w handles momentum
+// half (w & 1) of function (w >> 1), f or chi, so each lane keeps Q nodes of
+// one function.  Compared with the two-wave kernel this halves the state
+// held per wave (no register spill at Q = 16, four waves per SIMD) at the
+// price of computing the equilibrium coefficients of a half in both of its
+// waves.  Coupling through LDS and one barrier as in the two-wave kernel.
+template <int Q, int ADV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HHLB_QUARTER_WAVES))) void stage_kernel_quarter(
+    StageArgs A, const DevTables *__restrict__ tb, const DevChannel *__restrict__ chans,
+    const DevWindow *__restrict__ wins, const double *__restrict__ inv_dx,
+    const double *__restrict__ gw, const double *__restrict__ in_f,
+    const double *__restrict__ in_c) {
+  constexpr int H = Q;
+  constexpr bool kMfma = HHLB_MFMA && (H == 16);
+  __shared__ double s_part[2][6][64];
+  __shared__ double s_nw[2];
+  __shared__ double s_T[kMfma ? 4 * 64 * 16 : 1];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int hw = wv & 1, fn = wv >> 1;
+  const int lane = threadIdx.x & 63;
+  const int w = A.xcd_map ? xcd_window(blockIdx.x, A.nwin) : (int)blockIdx.x;
+  const DevWindow win = wins[w];
+  const DevChannel C = chans[win.ch];
+  const int Nx = C.Nx;
+  const int i = win.i0 - kHalo + lane;
+  const bool inside = i >= 0 && i < Nx;
+  const int kb0 = hw * H;
+  const double sg = hw ? -1.0 : 1.0;
+  const double *yin = (fn == 0 ? in_f : in_c) + C.off + (int64_t)kb0 * Nx;
+
+  double y[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) y[j] = inside ? yin[(int64_t)j * Nx + i] : 0.0;
+
+  // ---- closure, part 1: incoming ghosts of this wave's function; the f
+  // waves also balance the wall flux (Eq. nplus_def) ----
+  const bool needL = win.i0 < kHalo;
+  const bool needR = win.i0 - kHalo + 63 >= Nx;
+  double nw_mine = 0.0;
+  if ((hw == 1 && needL) || (hw == 0 && needR)) {
+    const bool left = hw == 1;
+    const int l0 = left ? kHalo : Nx - 1 - (win.i0 - kHalo);
+    const int dl = left ? 1 : -1;
+    const int gi = left ? -i : i - Nx + 1;
+    const double c0 = gi == 1 ? 3.0 : (gi == 2 ? 6.0 : 10.0);
+    const double c1 = gi == 1 ? -3.0 : (gi == 2 ? -8.0 : -15.0);
+    const double c2 = gi == 1 ? 1.0 : (gi == 2 ? 3.0 : 6.0);
+    const bool is_ghost = gi >= 1 && gi <= 3;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const double y0 = readlane_d(y[j], l0), y1 = readlane_d(y[j], l0 + dl),
+                   y2 = readlane_d(y[j], l0 + 2 * dl);
+      if (lane == j) { a0 = y0; a1 = y1; a2 = y2; }
+      if (is_ghost) y[j] = c0 * y0 + c1 * y1 + c2 * y2;
+    }
+    if (fn == 0) {
+      const double g1 = 3.0 * a0 - 3.0 * a1 + a2, g2 = 6.0 * a0 - 8.0 * a1 + 3.0 * a2;
+      const double fv = face_value<ADV>(a2, a1, a0, g1, g2);
+      const double acc = wave_sum(lane < H ? tb->p[kb0 + (lane < H ? lane : 0)] * fv : 0.0);
+      nw_mine = -acc * (left ? C.inv_DL : C.inv_DR);
+    }
+  }
+
+  // ---- partial moments: f waves n, n u, sum p^2 f and kb.f; chi waves
+  // sum chi and kb.chi ----
+  if (fn == 0) {
+    double pn = 0.0, pm = 0.0, ps = 0.0, pb = 0.0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const double v = tb->p[kb0 + j];
+      pn += y[j];
+      pm += v * y[j];
+      ps += v * v * y[j];
+      pb += tb->kb[j] * y[j];
+    }
+    s_part[hw][0][lane] = pn;
+    s_part[hw][1][lane] = pm;
+    s_part[hw][2][lane] = ps;
+    s_part[hw][4][lane] = pb;
+    if (lane == 0) s_nw[hw] = nw_mine;
+  } else {
+    double pc = 0.0, pb = 0.0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      pc += y[j];
+      pb += tb->kb[j] * y[j];
+    }
+    s_part[hw][3][lane] = pc;
+    s_part[hw][5][lane] = pb;
+  }
+  __syncthreads();
+  double n = s_part[0][0][lane] + s_part[1][0][lane];
+  double mom = s_part[0][1][lane] + s_part[1][1][lane];
+  const double s2 = s_part[0][2][lane] + s_part[1][2][lane];
+  const double ech = s_part[0][3][lane] + s_part[1][3][lane];
+  const double bproj = s_part[0][4 + fn][lane] + s_part[1][4 + fn][lane];
+  const double nL = s_nw[1], nR = s_nw[0];
+
+  // ---- closure, part 2: emergent ghosts ----
+  const double fscale_L = fn == 0 ? 1.0 : C.half_Dt * C.TL;
+  const double fscale_R = fn == 0 ? 1.0 : C.half_Dt * C.TR;
+  if (hw == 0 && i < 0) {
+    const double *gwL = gw + C.gw_off;
+#pragma unroll
+    for (int j = 0; j < H; ++j) y[j] = fscale_L * nL * gwL[j];
+  }
+  if (hw == 1 && i >= Nx && i <= Nx + 2) {
+    const double *gwR = gw + C.gw_off + 2 * H + H;
+#pragma unroll
+    for (int j = 0; j < H; ++j) y[j] = fscale_R * nR * gwR[j];
+  }
+  if (fn == 0 && A.nwall && A.stage == 2 && lane == 0) {
+    if (hw == 1 && win.i0 == 0) A.nwall[2 * win.ch] = nL;
+    if (hw == 0 && win.i0 <= Nx - 1 && Nx - 1 < win.i0 + kWin) A.nwall[2 * win.ch + 1] = nR;
+  }
+
+  // ---- moments (Eq. fmoms) ----
+  if (!inside) n = 1.0, mom = 0.0;
+  const double u = mom / n;
+  double T = (s2 - u * mom + 2.0 * ech) * C.inv_1pDt / n;
+  if (!inside) T = 1.0;
+  const double inv_tau = n * C.inv_Kn;
+
+  // ---- equilibrium coefficients of this half (as in the two-wave kernel) ----
+  double G[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) G[l] = 0.0;
+  if (C.inv_Kn != 0.0) {
+    const double sT = sqrt(T);
+    const double ub = sg * u * tb->inv_p0, s = sT * tb->inv_p0, y0 = -u / sT;
+    auto accum = [&](double x, double wt) {
+      double qm = 1.0, q = x - tb->a[0];
+      G[0] += wt;
+      if (Q > 1) G[1] += wt * q;
+#pragma unroll
+      for (int l = 1; l + 1 < Q; ++l) {
+        const double qn = (x - tb->a[l]) * q - tb->mb[l] * qm;
+        qm = q; q = qn;
+        G[l + 1] += wt * q;
+      }
+    };
+#pragma unroll 1
+    for (int j = 0; j < tb->nm; ++j) accum(ub + s * tb->zm[j], tb->wm[j]);
+    const double ymax = wave_max(inside ? fabs(y0) : 0.0);
+    if (ymax > 0.0) {
+      int li = kLadder - 1;
+      for (int j = 1; j < kLadder; ++j)
+        if (tb->lad_y[j] >= ymax) { li = j; break; }
+      const int nc = tb->lad_n[li], o = tb->lad_off[li];
+      for (int j = 0; j < nc; ++j) {
+        const double t = tb->ltau[o + j];
+        const double yt = y0 * t;
+        const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
+        accum(ub * (1.0 - t), -sg * e);
+      }
+    }
+  }
+
+  const bool out_lane = lane >= kHalo && lane < kHalo + kWin && inside;
+  const int ic = inside ? i : 0;
+  const double dx_inv = inv_dx[C.cell_off + ic];
+  const int64_t obase = C.off + (int64_t)kb0 * Nx;
+  const double gforce = C.g, dt = C.dt;
+  const bool wall_face = hw == 0 ? (i == -1) : (i == Nx - 1);
+  const double eqc = fn == 0 ? 1.0 : C.half_Dt * T;
+
+  // pass 1: local source -F (K y)_k - (y_k - y^eq_k)/tau
+  double src[H];
+  if constexpr (kMfma) {
+    double *Tw = s_T + wv * 64 * 16;
+    double aK[4], aH[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      aK[kc] = tb->Kin[(lane & 15) * H + 4 * kc + (lane >> 4)];
+      aH[kc] = tb->HWs[(lane & 15) * Q + 4 * kc + (lane >> 4)];
+    }
+    double geq[H], ky[H];
+    mfma_contract16_sw(aH, G, geq, Tw, lane);
+    mfma_contract16_sw(aK, y, ky, Tw, lane);
+#pragma unroll
+    for (int j = 0; j < H; ++j)
+      src[j] = -gforce * sg * (ky[j] + tb->ka[j] * bproj) - (y[j] - eqc * n * geq[j]) * inv_tau;
+  } else {
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      double acc = 0.0, kf = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) acc += tb->HWs[j * Q + l] * G[l];
+#pragma unroll
+      for (int jj = 0; jj < H; ++jj) kf += tb->Kin[j * H + jj] * y[jj];
+      src[j] = -gforce * sg * (kf + tb->ka[j] * bproj) - (y[j] - eqc * n * acc) * inv_tau;
+    }
+  }
+
+  // pass 2: advection and the RK-3 combination, y^n prefetched
+  constexpr int PD = HHLB_PREFETCH < H ? HHLB_PREFETCH : H;
+  const bool need_base = A.a_base != 0.0;
+  const double *bptr = (const double *)(fn == 0 ? A.base_f : A.base_c) + obase + ic;
+  double *optr = (double *)(fn == 0 ? A.out_f : A.out_c) + obase + ic;
+  double bq[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) bq[d] = need_base ? bptr[(int64_t)d * Nx] : 0.0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double v = tb->p[kb0 + j];
+    const double base = bq[j % PD];
+    if (j + PD < H) bq[j % PD] = need_base ? bptr[(int64_t)(j + PD) * Nx] : 0.0;
+    const double y0v = y[j];
+    double F;
+    if (hw == 0) {
+      const double ym1 = dpp_shr1(y0v), ym2 = dpp_shr1(ym1);
+      const double yp1 = dpp_shl1(y0v), yp2 = dpp_shl1(yp1);
+      F = v * face_value<ADV>(ym2, ym1, y0v, yp1, yp2);
+      if (wall_face) F = v * y0v;
+    } else {
+      const double ym1 = dpp_shr1(y0v);
+      const double yp1 = dpp_shl1(y0v), yp2 = dpp_shl1(yp1), yp3 = dpp_shl1(yp2);
+      F = v * face_value<ADV>(yp3, yp2, yp1, y0v, ym1);
+      if (wall_face) F = v * yp1;
+    }
+    const double Fl = dpp_shr1(F);
+    const double L = -(F - Fl) * dx_inv + src[j];
+    const double yn = A.a_base * base + A.b_stage * (y0v + dt * L);
+    if (out_lane) optr[(int64_t)j * Nx] = yn;
+    if ((j + 1) % HHLB_SCHED_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
   }
 }
 

@@ -33,10 +33,12 @@ def initial_states(channels, seed=0, perturb=0.0, n0=1.0, u0=0.0, T0=1.0):
     return out
 
 
-def run_gpu(channels, states, nsteps, precision=0):
+def run_gpu(channels, states, nsteps, precision=0, tuning=None):
     import torch
     import paper_1708_03249_amd as H
     s = H.Solver(channels, precision=precision)
+    if tuning:
+        s.set_tuning(**tuning)
     f = torch.from_numpy(np.concatenate([st[0].ravel() for st in states])).cuda()
     c = torch.from_numpy(np.concatenate([st[1].ravel() for st in states])).cuda()
     s.set_state(f, c if s.has_chi else None)

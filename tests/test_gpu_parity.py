@@ -33,10 +33,10 @@ def H():
     return H
 
 
-def _check(channels, nsteps, perturb=0.0, seed=0, tol=TOL, which=None, what=""):
+def _check(channels, nsteps, perturb=0.0, seed=0, tol=TOL, which=None, what="", tuning=None):
     print(f"[parity] {what}: {len(channels)} channels, {nsteps} steps", flush=True)
     states = initial_states(channels, seed=seed, perturb=perturb)
-    gpu = run_gpu(channels, states, nsteps)
+    gpu = run_gpu(channels, states, nsteps, tuning=tuning)
     assert gpu["bad"] == 0
     ref = run_oracle(channels, states, nsteps, gpu["dt"], which=which)
     return compare(channels, gpu, ref, tol=tol, what=what)
@@ -273,7 +273,9 @@ def test_launch_configurations_bit_identical(form):
         assert np.array_equal(outs[0][0], outs[k][0]), configs[k]
         assert np.array_equal(outs[0][1], outs[k][1]), configs[k]
     # autotune: direct launches x {one stream, class streams} x 2 mappings and
-    # 16-step graphs x 2 mappings, (trial + 1) steps each
+    # 16-step graphs x 2 mappings, for 2 and (FP64 form) 4 waves per window,
+    # (trial + 1) steps each; the four-wave kernel rounds differently from the
+    # two-wave one, so the comparison solver replays the same configurations
     s = h.Solver(chans, precision=prec)
     s.set_state(f0, c0)
     best = s.autotune(trial_steps=2)
@@ -282,7 +284,11 @@ def test_launch_configurations_bit_identical(form):
     f, c = s.get_state()
     r = h.Solver(chans, precision=prec)
     r.set_state(f0, c0)
-    r.step(6 * 3 + 1)
+    for wpw in ((2, 4) if form == "fp64" else (2,)):
+        r.set_tuning(waves_per_window=wpw)
+        r.step(6 * 3)
+    r.set_tuning(**{k: best[k] for k in ("graph_steps", "class_streams", "xcd_map", "waves_per_window")})
+    r.step(1)
     fr, cr = r.get_state()
     torch.cuda.synchronize()
     assert np.array_equal(f.cpu().numpy(), fr.cpu().numpy())
@@ -318,3 +324,24 @@ def test_residual_against_oracle_rhs(form, tol):
         r = max(np.abs(Lf).max() / np.abs(fk).max(), np.abs(Lc).max() / np.abs(ck).max())
         assert abs(res[k] / r - 1) < tol, (form, k, res[k], r)
     s.close()
+
+
+def test_four_waves_per_window_against_oracle():
+    """The four-wave kernel (one wave per momentum half and function) on the
+    stretched three-Kn batch, HHLB(15;16) and the edge batch, against the
+    oracle (classes without the four-wave kernel keep the two-wave one)."""
+    h = H()
+    t4 = dict(waves_per_window=4)
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=8, Nx=200, adv=h.WENO5, stretch_A=0.9,
+                       T_left=1.0, T_right=2.0, g=-0.5, Kn=kn, dt=-0.5) for kn in (0.01, 0.1, 1.0)]
+    _check(chans, 60, perturb=0.05, what="stretched weno5, 4 waves", tuning=t4)
+    ch = h.Channel(quad=h.HALF_HERMITE, Q=16, Nx=150, adv=h.WENO5, stretch_A=0.9, T_left=1.0,
+                   T_right=1.5, g=-1.0, Kn=0.02, dt=-0.5)
+    _check([ch], 25, perturb=0.02, what="HHLB(15;16), 4 waves", tuning=t4)
+    edge = [h.Channel(quad=h.HALF_HERMITE, Q=6, N=3, Nx=8, adv=h.WENO5, transverse_dof=2,
+                      Kn=math.inf, g=0.3, p0=1.2, T_left=1.2, T_right=0.8, dt=2e-4),
+            h.Channel(quad=h.HALF_HERMITE, Q=1, N=0, Nx=59, adv=h.UPWIND3, transverse_dof=2,
+                      Kn=0.3, g=-0.2, dt=1e-3),
+            h.Channel(quad=h.HALF_HERMITE, Q=4, Nx=117, adv=h.UPWIND3, transverse_dof=0, Kn=0.2,
+                      g=-0.2, T_right=1.1, dt=-0.4)]
+    _check(edge, 80, perturb=0.03, seed=5, what="edge batch, 4 waves", tuning=t4)
