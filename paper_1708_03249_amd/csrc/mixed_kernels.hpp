@@ -29,8 +29,17 @@
 #pragma once
 #include "step_kernels.hpp"
 
+// Launch shape of the mixed kernel (measured on the large workload):
+// the moment partials share the tiles' LDS (17 KB per block instead of 23),
+// four waves per SIMD (128 registers), y^n operands six node-functions ahead.
+#ifndef HHLB_MIXED_ALIAS
+#define HHLB_MIXED_ALIAS 1
+#endif
+#ifndef HHLB_PREFETCH_MIXED
+#define HHLB_PREFETCH_MIXED 6
+#endif
 #ifndef HHLB_MIXED_WAVES
-#define HHLB_MIXED_WAVES 3
+#define HHLB_MIXED_WAVES 4
 #endif
 
 namespace hhlb {
@@ -96,6 +105,56 @@ __device__ __forceinline__ void add_to_state(float hi, int16_t lo, float delta, 
   // denormal sums
   const float q = __builtin_rintf(ldexpf(e, 39 - __builtin_amdgcn_frexp_expf(s)));
   lo_out = (int16_t)fminf(fmaxf(q, -32767.0f), 32767.0f);
+}
+
+// Lane-parallel WENO-5 in FP32: the triple decomposition of weno5_lanes
+// (FaceCoef) with the power-of-two rescaling of weno5f, which the FP32 range
+// needs in smooth flow (unscaled products of four sigmas underflow there).
+struct FaceCoefF {
+  float dl, dc, dr, el, gl, ec, er, gr;
+};
+__device__ __forceinline__ FaceCoefF face_coef_f(int hw) {
+  const FaceCoef c = face_coef(hw);
+  return FaceCoefF{(float)c.dl, (float)c.dc, (float)c.dr, (float)c.el, (float)c.gl,
+                   (float)c.ec, (float)c.er, (float)c.gr};
+}
+__device__ __forceinline__ float weno5f_lanes(float y, const FaceCoefF &c, bool used) {
+  const float ym = dpp_shr1f(y), yp = dpp_shl1f(y);
+  const float D2 = fmaf(-2.0f, y, ym) + yp;
+  const float E = (float)kHalfKappa * (yp - ym);
+  const float A = D2 * D2;
+  const float bC = fmaf(E, E, A);
+  const float tL = fmaf((float)kKappa, D2, E), tR = fmaf((float)kKappa, D2, -E);
+  const float bL = fmaf(tL, tL, A), bR = fmaf(tR, tR, A);
+  const float fL = fmaf(c.gl, D2, fmaf(c.el, E, y));
+  const float fC = fmaf(1.0f / 12.0f, D2, fmaf(c.ec, E, y));
+  const float fR = fmaf(c.gr, D2, fmaf(c.er, E, y));
+  const float sL = dpp_shr1f(bL), FL = dpp_shr1f(fL);
+  const float sR = dpp_shl1f(bR), FR = dpp_shl1f(fR);
+  const int ex = __builtin_amdgcn_frexp_expf(fmaxf(sL, fmaxf(bC, sR)));
+  const float rL = ldexpf(sL, -ex), rC = ldexpf(bC, -ex), rR = ldexpf(sR, -ex);
+  const float qL = rL * rL, qC = rC * rC, qR = rR * rR;
+  float wL = c.dl * (qC * qR), wC = c.dc * (qL * qR), wR = c.dr * (qL * qC);
+  float dd = wL + wC + wR;
+  if (!(dd > 1e-37f) && used) {   // limit rule, as in weno5f
+    const float tiny = 1e-17f;
+    wL = qL < tiny ? c.dl : 0.0f;
+    wC = qC < tiny ? c.dc : 0.0f;
+    wR = qR < tiny ? c.dr : 0.0f;
+    dd = wL + wC + wR;
+  }
+  return fmaf(wL, FL, fmaf(wC, fC, wR * FR)) * __builtin_amdgcn_rcpf(dd);
+}
+__device__ __forceinline__ float upwind3f_lanes(float y, const FaceCoefF &c) {
+  const float ym = dpp_shr1f(y), yp = dpp_shl1f(y);
+  const float D2 = fmaf(-2.0f, y, ym) + yp;
+  const float E = (float)kHalfKappa * (yp - ym);
+  return fmaf(1.0f / 12.0f, D2, fmaf(c.ec, E, y));
+}
+template <int ADV>
+__device__ __forceinline__ float face_value_f_lanes(float y, const FaceCoefF &c, bool used) {
+  if constexpr (ADV == 0) return weno5f_lanes(y, c, used);
+  else return upwind3f_lanes(y, c);
 }
 
 template <int ADV>
@@ -230,11 +289,20 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
   constexpr int NC = NFUN;
   constexpr bool kMfmaEq = HHLB_MFMA && (H == 16);                          // FP64 equilibrium table
   constexpr bool kMfmaK = PREC != kPrecF32 || (HHLB_MFMA && H == 16);       // force block
-  __shared__ double s_part[2][6][64];
   __shared__ double s_nw[2];
   // per-wave transpose tiles: 64 x 17 doubles for the FP64 equilibrium
   // table, 64 x 17 floats when only the force block uses the matrix cores
-  __shared__ double s_T[kMfmaEq ? 2 * 64 * 17 : (kMfmaK ? 64 * 17 : 1)];
+  constexpr int kTile = kMfmaEq ? 2 * 64 * 17 : (kMfmaK ? 64 * 17 : 1);
+#if HHLB_MIXED_ALIAS
+  // the moment partials share the tiles' memory (a barrier separates them)
+  constexpr int kLds = kTile > 2 * 6 * 64 ? kTile : 2 * 6 * 64;
+  __shared__ double s_lds[kLds];
+  double (*s_part)[6][64] = reinterpret_cast<double (*)[6][64]>(s_lds);
+  double *s_T = s_lds;
+#else
+  __shared__ double s_part[2][6][64];
+  __shared__ double s_T[kTile];
+#endif
   const int hw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int w = A.xcd_map ? xcd_window(blockIdx.x, A.nwin) : (int)blockIdx.x;
@@ -327,6 +395,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
   const double ech = s_part[0][3][lane] + s_part[1][3][lane];
   const float bf = (float)(s_part[0][4][lane] + s_part[1][4][lane]);
   const float bc = (float)(s_part[0][5][lane] + s_part[1][5][lane]);
+#if HHLB_MIXED_ALIAS
+  __syncthreads();   // the tiles below overwrite the partials
+#endif
   const double nL = s_nw[1], nR = s_nw[0];
 
   // ---- closure, part 2: emergent ghosts phi = n_w g^w_k / w_k ----
@@ -401,7 +472,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
   const float dx_inv = (float)inv_dx[C.cell_off + ic];
   const int64_t obase = C.off + (int64_t)kb0 * Nx;
   const float gforce = (float)C.g, dt = (float)C.dt;
-  const bool wall_face = hw == 0 ? (i == -1) : (i == Nx - 1);
+  // lane i forms the face value at i+1/2 (hw = 0) or i-1/2 (hw = 1); the
+  // other face of its cell comes from the neighbouring lane
+  const FaceCoefF fcoef = face_coef_f(hw);
+  const bool face_used = inside && lane >= kHalo - 1 + hw && lane < kHalo + kWin + hw;
+  const bool wall_face = hw == 0 ? (i == -1) : (i == Nx);
+  const float sdx = hw == 0 ? -dx_inv : dx_inv;   // L = sdx (F - F_other) + source
 
   // pass 1: local sources in FP32: -F (K y)_k - (y_k - y^eq_k)/tau
   float srcf[H], srcc[NC > 1 ? H : 1];
@@ -492,23 +568,37 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
       }
     }
   }
+  // keep the finished sources in registers: without this fence the compiler
+  // sinks their terms into pass 2 and holds several values per node
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    asm volatile("" : "+v"(srcf[j]));
+    if constexpr (NC > 1) asm volatile("" : "+v"(srcc[j]));
+  }
 
   // pass 2: advection and the RK-3 combination, FP32, in increment form.
   // The stage increment (and, in the last stage, hi and lo of y^n) are
-  // loaded HHLB_PREFETCH node-functions ahead of their use.
+  // loaded HHLB_PREFETCH_MIXED node-functions ahead of their use.
   const bool last = A.stage == 2;
   constexpr int NSEC = H * NC;
-  constexpr int PD = HHLB_PREFETCH < NSEC ? HHLB_PREFETCH : NSEC;
-  auto off_of = [&](int sec) { return obase + (int64_t)(sec / NC) * Nx + ic; };
+  constexpr int PD = HHLB_PREFETCH_MIXED < NSEC ? HHLB_PREFETCH_MIXED : NSEC;
+  // uniform base of population row r of an array, opaque at its point of
+  // use: otherwise the compiler precomputes the bases of every row up front
+  // and spills them
+  auto row = [&](auto *base, int r) {
+    auto *p = base + obase + (int64_t)r * Nx;
+    asm volatile("" : "+s"(p));
+    return p;
+  };
   float dq[PD], hq[PD];
   int16_t lq[PD];
   auto fetch = [&](int sec, int slot) {
-    const int64_t o = off_of(sec);
+    const int r = sec / NC;
     const bool f0 = (sec % NC) == 0;
-    dq[slot] = has_d ? (f0 ? d_f : d_c)[o] : 0.0f;
+    dq[slot] = has_d ? row(f0 ? d_f : d_c, r)[ic] : 0.0f;
     if (last) {
-      hq[slot] = (f0 ? hi_f : hi_c)[o];
-      lq[slot] = (f0 ? A.lo_in_f : A.lo_in_c)[o];
+      hq[slot] = row(f0 ? hi_f : hi_c, r)[ic];
+      lq[slot] = row(f0 ? A.lo_in_f : A.lo_in_c, r)[ic];
     } else {
       hq[slot] = 0.0f;
       lq[slot] = 0;
@@ -528,31 +618,21 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
       if (sec + PD < NSEC) fetch(sec + PD, sec % PD);
       const float y0v = fn == 0 ? yf[j] : yc[j];
       const float src = fn == 0 ? srcf[j] : srcc[j];
-      float F;
-      if (hw == 0) {
-        const float ym1 = dpp_shr1f(y0v), ym2 = dpp_shr1f(ym1);
-        const float yp1 = dpp_shl1f(y0v), yp2 = dpp_shl1f(yp1);
-        F = v * face_value_f<ADV>(ym2, ym1, y0v, yp1, yp2);
-        if (wall_face) F = v * y0v;
-      } else {
-        const float ym1 = dpp_shr1f(y0v);
-        const float yp1 = dpp_shl1f(y0v), yp2 = dpp_shl1f(yp1), yp3 = dpp_shl1f(yp2);
-        F = v * face_value_f<ADV>(yp3, yp2, yp1, y0v, ym1);
-        if (wall_face) F = v * yp1;
-      }
-      const float Fl = dpp_shr1f(F);
-      const float L = -(F - Fl) * dx_inv + src;
-      const int64_t o = obase + (int64_t)j * Nx + ic;
+      float fv = face_value_f_lanes<ADV>(y0v, fcoef, face_used);
+      if (wall_face) fv = y0v;
+      const float F = v * fv;
+      const float Fo = hw == 0 ? dpp_shr1f(F) : dpp_shl1f(F);
+      const float L = fmaf(sdx, F - Fo, src);
       const float inc = b_inc * (din + dt * L);
       if (!last) {
-        if (out_lane) ((float *)(fn == 0 ? A.out_f : A.out_c))[o] = inc;
+        if (out_lane) row((float *)(fn == 0 ? A.out_f : A.out_c), j)[ic] = inc;
       } else {
         float hn;
         int16_t ln;
         add_to_state(hi, lo, inc, hn, ln);
         if (out_lane) {
-          ((float *)(fn == 0 ? A.out_f : A.out_c))[o] = hn;
-          (fn == 0 ? A.lo_out_f : A.lo_out_c)[o] = ln;
+          row((float *)(fn == 0 ? A.out_f : A.out_c), j)[ic] = hn;
+          row(fn == 0 ? A.lo_out_f : A.lo_out_c, j)[ic] = ln;
         }
       }
       // a scheduling fence after every HHLB_SCHED_GROUP node-functions:

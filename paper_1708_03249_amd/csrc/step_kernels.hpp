@@ -20,9 +20,13 @@ constexpr int kLadderPts = 64; // total points over the ladder
 constexpr int kWin = 58;       // output cells per wavefront
 
 // Build-time tuning switches of the half-range kernel: matrix cores for the
-// two 16 x 16 contractions (Q = 16) and the occupancy target.
+// two 16 x 16 contractions (Q = 16), the moment partials sharing the
+// transpose tiles' LDS, and the occupancy target.
 #ifndef HHLB_MFMA
 #define HHLB_MFMA 1
+#endif
+#ifndef HHLB_HALF_ALIAS
+#define HHLB_HALF_ALIAS 1
 #endif
 #ifndef HHLB_HALF_WAVES
 #define HHLB_HALF_WAVES 3
@@ -35,9 +39,9 @@ constexpr int kWin = 58;       // output cells per wavefront
 #define HHLB_SCHED_GROUP 1
 #endif
 // how many node-functions ahead the advection pass loads the values of y^n
-// (and, in the mixed form, the stage increments and correction words)
+// (the mixed kernel has its own distance, HHLB_PREFETCH_MIXED)
 #ifndef HHLB_PREFETCH
-#define HHLB_PREFETCH 3
+#define HHLB_PREFETCH 4
 #endif
 constexpr int kHalo = 3;
 
@@ -203,6 +207,90 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
     dd = n1 + n2 + n3;
   }
   return (n1 * F1 + n2 * F2 + n3 * F3) * recip(dd);
+}
+
+// Lane-parallel WENO-5 of the half-range kernels: lane i holds cell i.
+// Every smoothness indicator and candidate value of Eqs. (weno_sigma) and
+// (weno5_flux) depends on one triple of consecutive cells.  With
+// D2 = y_{m-1} - 2 y_m + y_{m+1} and D1 = y_{m+1} - y_{m-1} of the triple
+// centred on cell m:
+//   sigma: 13/12 D2^2 + (D2 + D1/2)^2,  13/12 D2^2 + (D1/2)^2,  13/12 D2^2 + (D2 - D1/2)^2
+//   F:     y_m + a D1 + b D2, (a, b) in {(+-3/4, 13/12), (+-1/4, 1/12)}.
+// Each lane evaluates them once for its own triple; the candidates of the
+// triples centred on i-1 and i+1 arrive by one DPP shift each.  The sigmas
+// are all scaled by 12/13 (a common factor cancels in the weights), which
+// leaves D2^2 + (kappa (D2 +- D1/2))^2 with kappa = sqrt(12/13).
+//   hw = 0 (p > 0): value at the face i+1/2 from cells i-2..i+2;
+//   hw = 1 (p < 0): value at the face i-1/2 from cells i+2..i-2 (mirrored).
+// The ideal weights (0.1, 0.6, 0.3) of the upwind-ordered candidates then
+// belong to the triples (i-1, i, i+1) for hw = 0 and (i+1, i, i-1) for hw = 1.
+struct FaceCoef {
+  double dl, dc, dr;   // ideal weights of the triples centred on i-1, i, i+1
+  double el, gl;       // candidate of triple i-1: y + el E + gl D2 (E = kappa D1 / 2)
+  double ec;           // candidate of triple i:   y + ec E + D2 / 12
+  double er, gr;       // candidate of triple i+1
+};
+constexpr double kKappa = 0.9607689228305228;         // sqrt(12/13)
+constexpr double kHalfKappa = 0.4803844614152614;     // sqrt(12/13) / 2
+__device__ __forceinline__ FaceCoef face_coef(int hw) {
+  const double h = 1.0 / (2.0 * kKappa);   // a = 1/4 in units of E
+  if (hw == 0) return FaceCoef{0.1, 0.6, 0.3, 3.0 * h, 13.0 / 12.0, h, -h, 1.0 / 12.0};
+  return FaceCoef{0.3, 0.6, 0.1, h, 1.0 / 12.0, -h, -3.0 * h, 13.0 / 12.0};
+}
+
+// The face value of the lane's cell (see FaceCoef).  `used` marks lanes whose
+// value is consumed: only they may send the wave into the rescaling branch.
+// The product-form weights delta_q prod_{r!=q} sigma_r^2 are formed directly;
+// when their sum leaves [1e-290, 1e290] the sigmas are rescaled by an exact
+// power of two and, if the sum still underflows, the limit of Table (weno)
+// applies (as in weno5).
+__device__ __forceinline__ double weno5_lanes(double y, const FaceCoef &c, bool used) {
+  const double ym = dpp_shr1(y), yp = dpp_shl1(y);
+  const double D2 = fma(-2.0, y, ym) + yp;
+  const double E = kHalfKappa * (yp - ym);
+  const double A = D2 * D2;
+  const double bC = fma(E, E, A);
+  const double tL = fma(kKappa, D2, E), tR = fma(kKappa, D2, -E);
+  const double bL = fma(tL, tL, A), bR = fma(tR, tR, A);
+  const double fL = fma(c.gl, D2, fma(c.el, E, y));
+  const double fC = fma(1.0 / 12.0, D2, fma(c.ec, E, y));
+  const double fR = fma(c.gr, D2, fma(c.er, E, y));
+  const double sL = dpp_shr1(bL), FL = dpp_shr1(fL);
+  const double sR = dpp_shl1(bR), FR = dpp_shl1(fR);
+  double qL = sL * sL, qC = bC * bC, qR = sR * sR;
+  double wL = c.dl * (qC * qR), wC = c.dc * (qL * qR), wR = c.dr * (qL * qC);
+  double dd = wL + wC + wR;
+  if (!(dd > 1e-290 && dd < 1e290) && used) {
+    const int ex = __builtin_amdgcn_frexp_exp(fmax(sL, fmax(bC, sR)));
+    const double rL = ldexp(sL, -ex), rC = ldexp(bC, -ex), rR = ldexp(sR, -ex);
+    qL = rL * rL; qC = rC * rC; qR = rR * rR;
+    wL = c.dl * (qC * qR); wC = c.dc * (qL * qR); wR = c.dr * (qL * qC);
+    dd = wL + wC + wR;
+    if (!(dd > 1e-250)) {
+      const double tiny = 1e-125;
+      wL = qL < tiny ? c.dl : 0.0;
+      wC = qC < tiny ? c.dc : 0.0;
+      wR = qR < tiny ? c.dr : 0.0;
+      dd = wL + wC + wR;
+    }
+  }
+  return fma(wL, FL, fma(wC, fC, wR * FR)) * recip(dd);
+}
+
+// Third-order upwind value of the lane's cell in the same orientation:
+// (-y_{i-1} + 5 y_i + 2 y_{i+1})/6 (hw = 0), (2 y_{i-1} + 5 y_i - y_{i+1})/6
+// (hw = 1), i.e. the central candidate y + ec E + D2/12.
+__device__ __forceinline__ double upwind3_lanes(double y, const FaceCoef &c) {
+  const double ym = dpp_shr1(y), yp = dpp_shl1(y);
+  const double D2 = fma(-2.0, y, ym) + yp;
+  const double E = kHalfKappa * (yp - ym);
+  return fma(1.0 / 12.0, D2, fma(c.ec, E, y));
+}
+
+template <int ADV>
+__device__ __forceinline__ double face_value_lanes(double y, const FaceCoef &c, bool used) {
+  if constexpr (ADV == 0) return weno5_lanes(y, c, used);
+  else return upwind3_lanes(y, c);
 }
 
 // Third-order upwind-biased face value (-f_{i-1} + 5 f_i + 2 f_{i+1})/6.
@@ -516,6 +604,31 @@ __device__ __forceinline__ void mfma_contract16(const double aM[4], const double
   __builtin_amdgcn_wave_barrier();
 }
 
+// mfma_contract16 without the read-back: OUT[i] of cell `lane` is left in
+// T[lane * 17 + i] for the caller.  Each block of 16 cells reads and writes
+// only its own 16 rows of T, so the blocks run one after another with one
+// accumulator (the caller holds many live values at this point).
+__device__ __forceinline__ void mfma_contract16_keep(const double aM[4], const double X[16], double *T,
+                                                     int lane) {
+  constexpr int S = 17;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) T[lane * S + k] = X[k];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const double b = T[(16 * cb + (lane & 15)) * S + 4 * kc + (lane >> 4)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aM[kc], b, acc, 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[(16 * cb + (lane & 15)) * S + 4 * r + (lane >> 4)] = acc[r];
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Half-range kernel: the two momentum halves of a window run in the two
 // wavefronts of a 128-thread block (wave 0: p > 0, wave 1: p < 0).  Each lane
 // holds the Q nodes of its half for f and chi; the only coupling between the
@@ -529,10 +642,19 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
     const double *__restrict__ in_c) {
   constexpr int H = Q;
   constexpr int NC = NFUN;
-  __shared__ double s_part[2][6][64];
   __shared__ double s_nw[2];
   constexpr bool kMfma = HHLB_MFMA && (H == 16);   // matrix cores for the 16 x 16 contractions
+#if HHLB_HALF_ALIAS
+  // the moment partials share the transpose tiles' memory (a barrier
+  // separates them)
+  constexpr int kLds = (kMfma ? 2 * 64 * 17 : 1) > 2 * 6 * 64 ? 2 * 64 * 17 : 2 * 6 * 64;
+  __shared__ double s_lds[kLds];
+  double (*s_part)[6][64] = reinterpret_cast<double (*)[6][64]>(s_lds);
+  double *s_T = s_lds;
+#else
+  __shared__ double s_part[2][6][64];
   __shared__ double s_T[kMfma ? 2 * 64 * 17 : 1];
+#endif
   const int hw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int w = A.xcd_map ? xcd_window(blockIdx.x, A.nwin) : (int)blockIdx.x;
@@ -617,6 +739,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
   const double bf = s_part[0][4][lane] + s_part[1][4][lane];
   const double bc = s_part[0][5][lane] + s_part[1][5][lane];
   const double nL = s_nw[1], nR = s_nw[0];
+#if HHLB_HALF_ALIAS
+  __syncthreads();   // the tiles below overwrite the partials
+#endif
 
   // ---- closure, part 2: emergent ghosts n_w g^w_k in all three cells ----
   if (hw == 0 && i < 0) {
@@ -690,11 +815,10 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
   const double dx_inv = inv_dx[C.cell_off + ic];
   const int64_t obase = C.off + (int64_t)kb0 * Nx;
   const double gforce = C.g, dt = C.dt;
-  const bool wall_face = hw == 0 ? (i == -1) : (i == Nx - 1);
 
   // pass 1: local source -F (K y)_k - (y_k - y^eq_k)/tau for f and chi,
   // with the equilibrium population g_k of this half
-  double srcf[H], srcc[NC > 1 ? H : 1];
+  double srcf[H], srcc[(NC > 1 && !kMfma) ? H : 1];
   const double eqc = C.half_Dt * T;
   if constexpr (kMfma) {
     // (K_in y) and (HWs G) as 16 x 16 x 64-cell products on the matrix cores
@@ -709,13 +833,19 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
     mfma_contract16(aH, G, geq, Tw, lane);
     mfma_contract16(aK, yf, ky, Tw, lane);
 #pragma unroll
-    for (int j = 0; j < H; ++j)
+    for (int j = 0; j < H; ++j) {
       srcf[j] = -gforce * sg * (ky[j] + tb->ka[j] * bf) - (yf[j] - n * geq[j]) * inv_tau;
+      // keep the finished source in a register: without this fence the
+      // compiler sinks its terms into pass 2 and holds three values per node
+      asm volatile("" : "+v"(srcf[j]));
+    }
     if constexpr (NC > 1) {
-      mfma_contract16(aK, yc, ky, Tw, lane);
+      // the chi source stays in the lane's row of the tile until pass 2
+      // reads it, which keeps 16 values out of the register file
+      mfma_contract16_keep(aK, yc, Tw, lane);
 #pragma unroll
       for (int j = 0; j < H; ++j)
-        srcc[j] = -gforce * sg * (ky[j] + tb->ka[j] * bc) - (yc[j] - eqc * n * geq[j]) * inv_tau;
+        Tw[lane * 17 + j] = -gforce * sg * (Tw[lane * 17 + j] + tb->ka[j] * bc) - (yc[j] - eqc * n * geq[j]) * inv_tau;
     }
   } else {
     double geq[H];
@@ -747,13 +877,19 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
   // pass 2: advection (WENO-5 / upwind-3 face fluxes, Sec. IV.C.2) and the
   // RK-3 combination.  The y^n values the combination needs are loaded
   // HHLB_PREFETCH node-functions ahead of their use, so that the memory
-  // latency overlaps the WENO arithmetic of the nodes in between.
+  // latency overlaps the WENO arithmetic of the nodes in between.  Lane i
+  // forms the face value at i+1/2 (hw = 0) or i-1/2 (hw = 1); the other face
+  // of its cell comes from the neighbouring lane.
   constexpr int NSEC = H * NC;
   constexpr int PD = HHLB_PREFETCH < NSEC ? HHLB_PREFETCH : NSEC;
   const bool need_base = A.a_base != 0.0;
   auto base_ptr = [&](int sec) {
     return (const double *)((sec % NC) == 0 ? A.base_f : A.base_c) + obase + (int64_t)(sec / NC) * Nx + ic;
   };
+  const FaceCoef fcoef = face_coef(hw);
+  const bool face_used = inside && lane >= kHalo - 1 + hw && lane < kHalo + kWin + hw;
+  const bool wall_face_l = hw == 0 ? (i == -1) : (i == Nx);
+  const double sdx = hw == 0 ? -dx_inv : dx_inv;   // L = sdx (F - F_other) + source
   double bq[PD];
 #pragma unroll
   for (int d = 0; d < PD; ++d) bq[d] = need_base ? *base_ptr(d) : 0.0;
@@ -766,21 +902,14 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
       const double base = bq[sec % PD];
       if (sec + PD < NSEC) bq[sec % PD] = need_base ? *base_ptr(sec + PD) : 0.0;
       const double y0v = fn == 0 ? yf[j] : yc[j];
-      const double src = fn == 0 ? srcf[j] : srcc[j];
-      double F;
-      if (hw == 0) {
-        const double ym1 = dpp_shr1(y0v), ym2 = dpp_shr1(ym1);
-        const double yp1 = dpp_shl1(y0v), yp2 = dpp_shl1(yp1);
-        F = v * face_value<ADV>(ym2, ym1, y0v, yp1, yp2);
-        if (wall_face) F = v * y0v;
-      } else {
-        const double ym1 = dpp_shr1(y0v);
-        const double yp1 = dpp_shl1(y0v), yp2 = dpp_shl1(yp1), yp3 = dpp_shl1(yp2);
-        F = v * face_value<ADV>(yp3, yp2, yp1, y0v, ym1);
-        if (wall_face) F = v * yp1;
-      }
-      const double Fl = dpp_shr1(F);
-      const double L = -(F - Fl) * dx_inv + src;
+      double src;
+      if constexpr (kMfma && NC > 1) src = fn == 0 ? srcf[j] : s_T[hw * 64 * 17 + lane * 17 + j];
+      else src = fn == 0 ? srcf[j] : srcc[j];
+      double fv = face_value_lanes<ADV>(y0v, fcoef, face_used);
+      if (wall_face_l) fv = y0v;
+      const double F = v * fv;
+      const double Fo = hw == 0 ? dpp_shr1(F) : dpp_shl1(F);
+      const double L = fma(sdx, F - Fo, src);
       const int64_t o = obase + (int64_t)j * Nx + ic;
       double *op = (double *)(fn == 0 ? A.out_f : A.out_c);
       const double yn = A.a_base * base + A.b_stage * (y0v + dt * L);

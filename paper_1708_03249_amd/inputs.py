@@ -12,6 +12,18 @@ def perturbation(seed: int, shape, amplitude: float) -> np.ndarray:
     return 1.0 + amplitude * rng.random(shape)
 
 
+def smooth_modulation(seed: int, rows: int, Nx: int, amplitude: float, max_waves: int = 3) -> np.ndarray:
+    """Smooth positive factors 1 + amplitude * sin(2 pi m_r (i + 1/2) / Nx + phi_r)
+    of shape (rows, Nx), with m_r ~ U{1..max_waves} and phi_r ~ U[0, 2 pi)
+    drawn per row (in this order).  Applied to a uniform state they give a
+    resolved, non-uniform one, like a developed channel flow."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = rng.integers(1, max_waves + 1, rows)
+    phi = rng.uniform(0.0, 2.0 * np.pi, rows)
+    x = (np.arange(Nx) + 0.5) / Nx
+    return 1.0 + amplitude * np.sin(2.0 * np.pi * m[:, None] * x[None, :] + phi[:, None])
+
+
 def batch_draws(n_channels: int, seed: int = 0):
     """Per-channel draws of the batched workload (in this order per channel):
     Nx ~ U{64..1024}, Q ~ U{4, 8, 12}, log10 Kn ~ U[-3, 1], g ~ U[-1, 0],
