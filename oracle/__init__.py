@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hhlb_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_hhlb.so")
 
-HALF, FULL = 0, 1
+HALF, FULL, LAGUERRE = 0, 1, 2   # half-range Hermite, full-range Hermite, half-range Laguerre
 WENO5, UPWIND3 = 0, 1
 
 
@@ -62,7 +62,7 @@ class Channel:
 
     @property
     def V(self) -> int:
-        return 2 * self.Q if self.quad == HALF else self.Q
+        return self.Q if self.quad == FULL else 2 * self.Q
 
     @property
     def n_eq(self) -> int:
@@ -103,7 +103,7 @@ def _p(a):
 
 def tables(quad: int, Q: int, p0: float = 1.0):
     """Return (p, w, K, K_within, K_delta) as float64 arrays."""
-    V = 2 * Q if quad == HALF else Q
+    V = Q if quad == FULL else 2 * Q
     p, w = np.zeros(V), np.zeros(V)
     K, Kin, Kd = np.zeros((V, V)), np.zeros((V, V)), np.zeros((V, V))
     r = lib().orc_tables_get(quad, Q, p0, _p(p), _p(w), _p(K), _p(Kin), _p(Kd))
@@ -120,7 +120,7 @@ def hh_coeffs(lmax: int) -> np.ndarray:
 
 
 def equilibrium(quad: int, Q: int, N: int, n: float, u: float, T: float, p0: float = 1.0):
-    V = 2 * Q if quad == HALF else Q
+    V = Q if quad == FULL else 2 * Q
     out = np.zeros(V)
     if lib().orc_equilibrium(quad, Q, N, p0, n, u, T, _p(out)) < 0:
         raise ValueError("oracle: bad equilibrium arguments")

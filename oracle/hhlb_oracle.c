@@ -39,12 +39,12 @@ typedef __float128 qf;
 #define ORC_QMAX 32            /* largest quadrature order the tables accept  */
 #define ORC_VMAX (2 * ORC_QMAX)
 
-enum { ORC_HALF = 0, ORC_FULL = 1 };
+enum { ORC_HALF = 0, ORC_FULL = 1, ORC_HALF_LAGUERRE = 2 };
 enum { ORC_WENO5 = 0, ORC_UPWIND3 = 1 };
 
 /* One channel: the paper's statement of the problem (Sec. IV.D and V). */
 typedef struct {
-  int32_t quad;   /* ORC_HALF (HHLB) or ORC_FULL (HLB)                       */
+  int32_t quad;   /* ORC_HALF (HHLB), ORC_FULL (HLB) or ORC_HALF_LAGUERRE    */
   int32_t Q;      /* quadrature order                                          */
   int32_t N;      /* equilibrium expansion order, 0 <= N < Q                   */
   int32_t Nx;     /* number of cells                                           */
@@ -116,6 +116,8 @@ static void hh_build_polys(orc_tables *t, int lmax) {
   }
 }
 
+/* Member l of the half-range family held in t->c (Horner on its monomial
+ * coefficients). */
 static qf hh_eval(const orc_tables *t, int l, qf z) {
   qf acc = 0;
   for (int s = l; s >= 0; --s) acc = acc * z + t->c[l][s];
@@ -139,12 +141,14 @@ typedef qf (*poly_fn)(const orc_tables *, int, qf);
 static qf he_eval_t(const orc_tables *t, int l, qf z) { (void)t; return he_eval(l, z); }
 
 /* Roots of the degree-n member of an orthogonal family by interlacing: the
- * roots of p_l separate those of p_{l+1}.  Plain bisection in __float128. */
+ * roots of p_l separate those of p_{l+1}.  Plain bisection in __float128.
+ * Every root of p_l lies below 4 + 3 sqrt(l) (Hermite families) or
+ * 4l + 4 (Laguerre, whose largest root is below 4l + 2). */
 static void family_roots(const orc_tables *t, poly_fn f, int n, qf lo_all, qf *roots) {
   qf prev[ORC_QMAX + 2];
   int nprev = 0;
   for (int l = 1; l <= n; ++l) {
-    qf hi_all = 4.0Q + 3.0Q * sqrtq((qf)l);
+    qf hi_all = t->quad == ORC_HALF_LAGUERRE ? 4.0Q * l + 4.0Q : 4.0Q + 3.0Q * sqrtq((qf)l);
     qf cur[ORC_QMAX + 2];
     for (int j = 0; j < l; ++j) {
       qf a = (j == 0) ? lo_all : prev[j - 1];
@@ -227,6 +231,75 @@ static int build_half(orc_tables *t, int Q, double p0) {
   return 0;
 }
 
+/* Laguerre polynomials L_l(z) = sum_s (-1)^s binom(l, s) z^s / s!, orthonormal
+ * on [0, inf) with omega(z) = exp(-z) (gamma_l = 1, Sec. IV.B.4), L_l(0) = 1.
+ * c[l][s] holds the coefficient of z^s, as for the half-range Hermite family. */
+static void lag_build_polys(orc_tables *t, int lmax) {
+  memset(t->c, 0, sizeof(t->c));
+  for (int l = 0; l <= lmax; ++l) {
+    qf binom = 1, fact = 1;   /* binom(l, s), s! */
+    for (int s = 0; s <= l; ++s) {
+      if (s > 0) { binom = binom * (qf)(l - s + 1) / (qf)s; fact *= (qf)s; }
+      t->c[l][s] = ((s % 2) ? -binom : binom) / fact;
+    }
+  }
+}
+
+/* Half-range Gauss-Laguerre rule and force matrix.
+ * Nodes: the Q roots of L_Q (Sec. IV.B.1 with phi_l = L_l).
+ * Weights: Eq. (wk_half), w_k = z_k / ((Q + 1)^2 L_{Q+1}(z_k)^2).
+ * Force matrix: Eq. (hh_Kk_L), with Phi^Q_0(z_k) = sum_{s<Q} L_s(z_k)
+ * (omega(0) = 1, L_s(0) = 1). */
+static int build_half_laguerre(orc_tables *t, int Q, double p0) {
+  t->quad = ORC_HALF_LAGUERRE; t->Q = Q; t->V = 2 * Q; t->H = Q; t->p0 = p0;
+  lag_build_polys(t, Q + 1);
+  qf r[ORC_QMAX + 2];
+  family_roots(t, hh_eval, Q, 0.0Q, r);
+  for (int k = 0; k < Q; ++k) {
+    t->z[k] = r[k];
+    qf lq1 = hh_eval(t, Q + 1, r[k]);
+    t->w[k] = r[k] / ((qf)(Q + 1) * (qf)(Q + 1) * lq1 * lq1);
+  }
+  for (int l = 0; l <= Q + 1; ++l)
+    for (int k = 0; k < Q; ++k) t->P[l][k] = hh_eval(t, l, t->z[k]);
+  int V = 2 * Q;
+  for (int k = 0; k < V; ++k) {
+    int kk = k % Q;
+    t->p[k] = (double)((k < Q ? 1 : -1) * (qf)p0 * t->z[kk]);
+    t->wd[k] = (double)t->w[kk];
+  }
+  qf Phi0[ORC_QMAX];
+  for (int k = 0; k < Q; ++k) {
+    qf acc = 0;
+    for (int s = 0; s < Q; ++s) acc += t->P[s][k];
+    Phi0[k] = acc;
+  }
+  for (int k = 0; k < V; ++k) {
+    int kk = k % Q;
+    qf sk = (k < Q) ? 1 : -1;
+    for (int kp = 0; kp < V; ++kp) {
+      int kq = kp % Q;
+      qf skp = (kp < Q) ? 1 : -1;
+      qf inner = 0;
+      for (int l = 0; l <= Q - 2; ++l) {
+        qf tail = 0;
+        for (int s = l + 1; s <= Q - 1; ++s) tail += t->P[s][kk];
+        inner += t->P[l][kq] * tail;
+      }
+      qf pref = t->w[kk] * sk / (qf)p0;
+      qf within = pref * (1 + sk * skp) / 2 * inner;
+      qf cross = -pref * Phi0[kk] * Phi0[kq] / 2;
+      /* the part of the cross term due to the delta term of Eq. (deltaf_full),
+       * +(omega(0)/2) sigma sigma' Phi_0 Phi_0' (as in build_half) */
+      qf delta = pref * sk * skp * Phi0[kk] * Phi0[kq] / 2;
+      t->Kin[k * V + kp] = (double)within;
+      t->Kd[k * V + kp] = (double)delta;
+      t->K[k * V + kp] = (double)(within + cross);
+    }
+  }
+  return 0;
+}
+
 /* Full-range Gauss-Hermite rule (Sec. IV.A): nodes are the roots of He_Q,
  * weights Eq. (H_wk) w_k = Q!/He_{Q+1}(z_k)^2, force matrix Eq. (H_Kk).
  * Only even Q (no node at p = 0, Sec. IV.A.1). */
@@ -274,6 +347,7 @@ static int build_tables(orc_tables *t, int quad, int Q, double p0) {
   if (Q < 1 || Q > ORC_QMAX || !(p0 > 0)) return -1;
   if (quad == ORC_HALF) return build_half(t, Q, p0);
   if (quad == ORC_FULL) return build_full(t, Q, p0);
+  if (quad == ORC_HALF_LAGUERRE) return build_half_laguerre(t, Q, p0);
   return -1;
 }
 
@@ -283,7 +357,8 @@ static int build_tables(orc_tables *t, int quad, int Q, double p0) {
 
 /* Half-range coefficients of the Maxwellian g(u, T; p) of Eq. (feq), by
  * their definition G^+_l = int_0^inf dp g h_l(p/p0) and
- * G^-_l = int_0^inf dp g(-p) h_l(p/p0) (Sec. IV.B.3), written through the
+ * G^-_l = int_0^inf dp g(-p) h_l(p/p0) (Sec. IV.B.3; h_l is the rule's
+ * orthonormal family, half-range Hermite or Laguerre), written through the
  * monomial moments  int_0^inf dp g (p/p0)^s = (2 m T/p0^2)^{s/2} I_s(zeta),
  * zeta = u sqrt(m/2T) (zeta -> -zeta for G^-), where
  *   I_s(zeta) = pi^{-1/2} int_0^inf y^s exp(-(y - zeta)^2) dy,
@@ -345,8 +420,8 @@ static void eq_full(const orc_tables *t, int N, qf u, qf T, double *gout) {
 }
 
 static void equilibrium(const orc_tables *t, int N, double u, double T, double *g) {
-  if (t->quad == ORC_HALF) eq_half(t, N, (qf)u, (qf)T, g);
-  else eq_full(t, N, (qf)u, (qf)T, g);
+  if (t->quad == ORC_FULL) eq_full(t, N, (qf)u, (qf)T, g);
+  else eq_half(t, N, (qf)u, (qf)T, g);   /* half-range Hermite or Laguerre */
 }
 
 /* ------------------------------------------------------------------------ */
