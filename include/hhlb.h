@@ -50,7 +50,14 @@ enum {
   HHLB_E_STATE = -6         /* call out of order (e.g. no workspace bound)     */
 };
 
-enum { HHLB_HALF_HERMITE = 0, HHLB_FULL_HERMITE = 1 };   /* quadrature kind   */
+/* Quadrature kind.
+ *  HHLB_HALF_HERMITE:  half-range Gauss-Hermite, omega(z) = exp(-z^2/2)/sqrt(2 pi)
+ *                      on each half axis, V = 2Q (HHLB(N;Q), Sec. IV.B).
+ *  HHLB_FULL_HERMITE:  full-range Gauss-Hermite, V = Q, Q even (HLB(N;Q), Sec. IV.A).
+ *  HHLB_HALF_LAGUERRE: half-range Gauss-Laguerre, omega(z) = exp(-z) on each half
+ *                      axis, V = 2Q: nodes the roots of L_Q, weights Eq. (wk_half),
+ *                      force matrix Eq. (hh_Kk_L).  FP64 form only. */
+enum { HHLB_HALF_HERMITE = 0, HHLB_FULL_HERMITE = 1, HHLB_HALF_LAGUERRE = 2 };
 enum { HHLB_WENO5 = 0, HHLB_UPWIND3 = 1 };              /* advection scheme  */
 /* Arithmetic form of a solver (hhlb_create).
  *  HHLB_FP64:       every step in FP64; state stored as f_k in FP64.
@@ -58,7 +65,7 @@ enum { HHLB_WENO5 = 0, HHLB_UPWIND3 = 1 };              /* advection scheme  */
  *                   advection, collision, force contraction and the RK-3
  *                   combination in FP32; moment sums, the wall-density flux
  *                   balance (Eq. nplus_def) and the equilibrium coefficients
- *                   in FP64.  Half-range model only.
+ *                   in FP64.  Half-range Gauss-Hermite model only.
  *  HHLB_MIXED_BF16, HHLB_MIXED_F16: as HHLB_MIXED_F32 with the force block
  *                   K y contracted on the matrix cores from BF16 / FP16
  *                   operands with FP32 accumulation. */
@@ -68,7 +75,7 @@ enum { HHLB_FP64 = 0, HHLB_MIXED_F32 = 1, HHLB_MIXED_BF16 = 2, HHLB_MIXED_F16 = 
  * Sec. V.A): quadrature kind and order Q, equilibrium order N, grid, Kn,
  * force, wall temperatures and time step. */
 typedef struct {
-  int32_t quad;            /* HHLB_HALF_HERMITE or HHLB_FULL_HERMITE                 */
+  int32_t quad;            /* HHLB_HALF_HERMITE, HHLB_FULL_HERMITE or HHLB_HALF_LAGUERRE */
   int32_t Q;               /* quadrature order (nodes per half axis for HHLB)        */
   int32_t N;               /* equilibrium order, 0 <= N < Q; N < 0 selects min(20,Q-1) */
   int32_t Nx;              /* number of cells, >= 8                                  */

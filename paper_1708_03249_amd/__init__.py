@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # HHLB_LIBRARY selects another build of the same library (e.g. a tuning variant)
 LIB_PATH = os.environ.get("HHLB_LIBRARY") or os.path.join(_HERE, "libhhlb.so")
 
-HALF_HERMITE, FULL_HERMITE = 0, 1
+HALF_HERMITE, FULL_HERMITE, HALF_LAGUERRE = 0, 1, 2
 WENO5, UPWIND3 = 0, 1
 FP64, MIXED_F32, MIXED_BF16, MIXED_F16 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "mixed_f32": MIXED_F32, "mixed_bf16": MIXED_BF16, "mixed_f16": MIXED_F16}
@@ -75,7 +75,7 @@ class Channel:
 
     @property
     def V(self) -> int:
-        return 2 * self.Q if self.quad == HALF_HERMITE else self.Q
+        return self.Q if self.quad == FULL_HERMITE else 2 * self.Q
 
     def _c(self) -> _CChannel:
         return _CChannel(self.quad, self.Q, self.N, self.Nx, self.adv, self.transverse_dof,
@@ -139,21 +139,21 @@ def _dptr(a: np.ndarray):
 
 
 def nodes(quad: int, Q: int, p0: float = 1.0):
-    V = 2 * Q if quad == HALF_HERMITE else Q
+    V = Q if quad == FULL_HERMITE else 2 * Q
     p, w = np.zeros(V), np.zeros(V)
     _check(lib().hhlb_nodes(quad, Q, p0, _dptr(p), _dptr(w)))
     return p, w
 
 
 def force_matrix(quad: int, Q: int, p0: float = 1.0):
-    V = 2 * Q if quad == HALF_HERMITE else Q
+    V = Q if quad == FULL_HERMITE else 2 * Q
     K = np.zeros((V, V))
     _check(lib().hhlb_force_matrix(quad, Q, p0, _dptr(K)))
     return K
 
 
 def equilibrium(quad: int, Q: int, N: int, n: float, u: float, T: float, p0: float = 1.0):
-    V = 2 * Q if quad == HALF_HERMITE else Q
+    V = Q if quad == FULL_HERMITE else 2 * Q
     g = np.zeros(V)
     _check(lib().hhlb_equilibrium(quad, Q, N, p0, n, u, T, _dptr(g)))
     return g

@@ -312,7 +312,8 @@ hhlb_status check_channel(const hhlb_channel &c, int idx) {
   auto bad = [&](const char *what) {
     return fail(HHLB_E_ARG, "channel " + std::to_string(idx) + ": " + what);
   };
-  if (c.quad != HHLB_HALF_HERMITE && c.quad != HHLB_FULL_HERMITE) return bad("unknown quadrature");
+  if (c.quad != HHLB_HALF_HERMITE && c.quad != HHLB_FULL_HERMITE && c.quad != HHLB_HALF_LAGUERRE)
+    return bad("unknown quadrature");
   if (c.Q < 1) return bad("Q must be >= 1");
   if (c.quad == HHLB_FULL_HERMITE && (c.Q % 2)) return bad("full-range Q must be even");
   int N = c.N < 0 ? std::min(20, c.Q - 1) : c.N;
@@ -368,7 +369,7 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
     d.sb[l] = (double)sqrtl(r.b[l]);
     d.isb[l] = (double)(1.0L / sqrtl(r.b[l]));
   }
-  if (h.quad == HHLB_HALF_HERMITE) {
+  if (hhlb::half_range(h.quad)) {
     for (int j = 0; j < r.H * r.H; ++j) d.Kin[j] = r.Kin[j];
     for (int k = 0; k < r.H; ++k) { d.ka[k] = r.ka[k]; d.kb[k] = r.kb[k]; }
     for (int k = 0; k < r.H; ++k)
@@ -390,15 +391,16 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
     for (int l = 0; l < h.Q + 1 && l < (int)r.b.size(); ++l) d.mb[l] = (double)r.b[l];
     std::vector<long double> inv_norm(h.Q);
     for (int l = 0; l < h.Q; ++l) { prod *= r.b[l]; inv_norm[l] = 1.0L / sqrtl(prod); }
-    if (h.quad == HHLB_HALF_HERMITE)
+    if (hhlb::half_range(h.quad))
       for (int k = 0; k < r.H; ++k)
         for (int l = 0; l < h.Q; ++l) {
           HWs[(size_t)k * h.Q + l] = l <= N ? (long double)r.HW[(size_t)k * h.Q + l] * inv_norm[l] : 0.0L;
           d.HWs[k * h.Q + l] = (double)HWs[(size_t)k * h.Q + l];
         }
   }
-  if (h.quad == HHLB_HALF_HERMITE) {
+  if (hhlb::half_range(h.quad)) {
     // main rule of the half-range equilibrium: M = ceil((N+1)/2) points
+    // (a half-range Gauss-Hermite rule for either half-range kind)
     const int M = (N + 2) / 2;
     hhlb::Rule rm;
     std::string err2;
@@ -451,7 +453,7 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
   // correction ladder (half range): point counts and the |y0| each covers
   const int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
   double limits[hhlb::kLadder] = {0};
-  if (h.quad == HHLB_HALF_HERMITE) hhlb::correction_limits(r, N, counts, hhlb::kLadder, 3e-16, limits);
+  if (hhlb::half_range(h.quad)) hhlb::correction_limits(r, N, counts, hhlb::kLadder, 3e-16, limits);
   int o = 0;
   for (int j = 0; j < hhlb::kLadder; ++j) {
     d.lad_n[j] = counts[j];
@@ -590,7 +592,7 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
     if (st) return st;
     if (precision != HHLB_FP64 && channels[c].quad != HHLB_HALF_HERMITE)
       return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) +
-                                          ": the mixed-precision forms cover the half-range model only");
+                                          ": the mixed-precision forms cover the half-range Hermite model only");
   }
   std::unique_ptr<hhlb_solver> s;
   try {
@@ -615,12 +617,14 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
         int st = hhlb::build_rule(h.quad, h.Q, h.p0, mc.rule, err);
         if (st) return fail(st, "channel " + std::to_string(c) + ": " + err);
         const int nf = h.transverse_dof > 0 ? 2 : 1;
-        auto lk = launchers().find({h.quad, h.Q, nf, h.adv, precision, 2});
+        // both half-range kinds run the half-range kernels (tables differ)
+        const int kq = hhlb::half_range(h.quad) ? HHLB_HALF_HERMITE : HHLB_FULL_HERMITE;
+        auto lk = launchers().find({kq, h.Q, nf, h.adv, precision, 2});
         if (lk == launchers().end())
           return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) + ": no kernel for quad=" +
                                               std::to_string(h.quad) + " Q=" + std::to_string(h.Q));
         mc.launch = lk->second;
-        auto lk4 = launchers().find({h.quad, h.Q, nf, h.adv, precision, 4});
+        auto lk4 = launchers().find({kq, h.Q, nf, h.adv, precision, 4});
         if (lk4 != launchers().end()) mc.launch4 = lk4->second;
         st = cached_tables(h, N, precision, mc.rule, mc.dev);
         if (st) return st;

@@ -1,9 +1,11 @@
 // Host table builder for the half-range (Sec. IV.B) and full-range
-// (Sec. IV.A) Gauss-Hermite lattice Boltzmann models.
+// (Sec. IV.A) Gauss-Hermite and the half-range Gauss-Laguerre lattice
+// Boltzmann models.
 //
 // Half-range Hermite polynomials are generated from their three-term
 // recurrence (Appendix B), whose coefficients come from a discretised
 // Stieltjes procedure on a fine composite Gauss-Legendre grid of [0, 40];
+// Laguerre polynomials from their exact recurrence;
 // nodes are the eigenvalues of the Jacobi matrix (Eq. hh_A_matrix; found by
 // Sturm-sequence bisection) and weights the Christoffel numbers
 // 1 / sum_{l<Q} h_l(z_k)^2.  Everything is evaluated in long double through
@@ -141,15 +143,23 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
   if (Q < 1 || Q > kQmaxTables) { err = "Q out of range"; return HHLB_E_ARG; }
   if (!(p0 > 0) || !std::isfinite(p0)) { err = "p0 must be positive"; return HHLB_E_ARG; }
   if (quad == kFull && (Q % 2)) { err = "full-range Q must be even (no node at p = 0)"; return HHLB_E_ARG; }
-  if (quad != kHalf && quad != kFull) { err = "unknown quadrature"; return HHLB_E_ARG; }
+  if (quad != kHalf && quad != kFull && quad != kHalfLag) { err = "unknown quadrature"; return HHLB_E_ARG; }
   r = Rule();
   r.quad = quad; r.Q = Q; r.p0 = p0;
-  r.V = quad == kHalf ? 2 * Q : Q;
+  r.V = half_range(quad) ? 2 * Q : Q;
   r.H = r.V / 2;
   const int V = r.V, H = r.H;
   const ld lp0 = p0;
   if (quad == kHalf) {
     stieltjes_half(Q + 2, r.a, r.b);
+  } else if (quad == kHalfLag) {
+    // omega = exp(-z): monic recurrence pi_{l+1} = (z - (2l+1)) pi_l - l^2 pi_{l-1},
+    // b_0 = int omega = 1
+    r.a.assign(Q + 2, 0);
+    r.b.assign(Q + 3, 0);
+    for (int l = 0; l < Q + 2; ++l) r.a[l] = 2 * l + 1;
+    r.b[0] = 1;
+    for (int l = 1; l <= Q + 2; ++l) r.b[l] = (ld)l * l;
   } else {
     // probabilists' Hermite: monic recurrence with a_l = 0, b_l = l, b_0 = 1
     r.a.assign(Q + 2, 0);
@@ -159,8 +169,9 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
   }
   // nodes and Christoffel weights
   std::vector<ld> ev;
-  ld hi = 8 + 4 * sqrtl((ld)Q);
-  jacobi_eigenvalues(r, Q, quad == kHalf ? 0 : -hi, hi, ev);
+  // node envelopes: 2.5 sqrt(Q) (Hermite families), 4Q (Laguerre)
+  ld hi = quad == kHalfLag ? 4 * (ld)Q + 8 : 8 + 4 * sqrtl((ld)Q);
+  jacobi_eigenvalues(r, Q, quad == kFull ? -hi : 0, hi, ev);
   std::vector<ld> h(Q + 2);
   std::vector<ld> zall(Q), wall(Q);
   for (int k = 0; k < Q; ++k) {
@@ -172,7 +183,7 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
   }
   r.z.resize(H);
   r.w.resize(H);
-  if (quad == kHalf) {
+  if (half_range(quad)) {
     for (int k = 0; k < H; ++k) { r.z[k] = zall[k]; r.w[k] = wall[k]; }
   } else {
     for (int k = 0; k < H; ++k) { r.z[k] = zall[H + k]; r.w[k] = wall[H + k]; }
@@ -180,14 +191,19 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
   // self-check: exactness for degree <= 2Q-1 against the weight's moments
   {
     std::vector<ld> mu(2 * Q + 1);
-    if (quad == kHalf) {
-      mu[0] = 0.5L;
-      mu[1] = 1 / sqrtl(2 * kPi);
+    if (quad == kHalfLag) {
+      mu[0] = 1;   // int z^s exp(-z) = s!
+      for (int s = 1; s <= 2 * Q; ++s) mu[s] = s * mu[s - 1];
     } else {
-      mu[0] = 1;
-      mu[1] = 0;
+      if (quad == kHalf) {
+        mu[0] = 0.5L;
+        mu[1] = 1 / sqrtl(2 * kPi);
+      } else {
+        mu[0] = 1;
+        mu[1] = 0;
+      }
+      for (int s = 2; s <= 2 * Q; ++s) mu[s] = (s - 1) * mu[s - 2];
     }
-    for (int s = 2; s <= 2 * Q; ++s) mu[s] = (s - 1) * mu[s - 2];
     for (int s = 0; s < 2 * Q; ++s) {
       ld acc = 0;
       for (int k = 0; k < Q; ++k) acc += wall[k] * powl(zall[k], s);
@@ -208,15 +224,22 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
     r.wv[k] = (double)r.w[kk];
   }
   r.K.assign((size_t)V * V, 0.0);
-  r.HW.assign((size_t)(quad == kHalf ? H : V) * Q, 0.0);
-  if (quad == kHalf) {
-    // Eq. (hh_Kk_hh) through the recurrence: h_{l,0} = h_l(0),
-    // h_{l,l}/h_{l+1,l+1} = 1/a_l = sqrt(b_{l+1}); Phi^Q_0 of Eq. (Phi_def_hh).
+  r.HW.assign((size_t)(half_range(quad) ? H : V) * Q, 0.0);
+  if (half_range(quad)) {
+    // Eq. (hh_Kk) through the recurrence.  The within-half block needs the
+    // expansion coefficients of the derivative, phi_s' = sum_{l<s} c_{s,l} phi_l;
+    // integrating by parts on [0, inf),
+    //   c_{s,l} = -omega(0) phi_s(0) phi_l(0) - int phi_s omega' phi_l.
+    // Hermite (omega' = -z omega): the integral is sqrt(b_s) for l = s-1
+    // (Eq. hh_Kk_hh, h_{l,l}/h_{l+1,l+1} = sqrt(b_{l+1})); Laguerre
+    // (omega' = -omega): it vanishes for l < s (Eq. hh_Kk_L).
+    // Phi^Q_0(z_k) = sum_{s<Q} phi_s(0) phi_s(z_k) (Eq. Phi_def).
     std::vector<ld> h0(Q + 1);
     ortho_values(r, Q, 0.0L, h0.data());
     std::vector<std::vector<ld>> hz(H, std::vector<ld>(Q + 1));
     for (int k = 0; k < H; ++k) ortho_values(r, Q, r.z[k], hz[k].data());
-    const ld s2pi = sqrtl(2 * kPi);
+    const bool lag = quad == kHalfLag;
+    const ld s2pi = lag ? 1.0L : sqrtl(2 * kPi);   // 1 / omega(0)
     std::vector<ld> Phi0(H);
     for (int k = 0; k < H; ++k) {
       ld acc = 0;
@@ -230,7 +253,7 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
         for (int l = 0; l <= Q - 2; ++l) {
           ld tail = 0;
           for (int s = l + 1; s <= Q - 1; ++s) tail += h0[s] * hz[k][s];
-          acc += hz[kp][l] * (h0[l] / s2pi * tail - sqrtl(r.b[l + 1]) * hz[k][l + 1]);
+          acc += hz[kp][l] * (h0[l] / s2pi * tail - (lag ? 0.0L : sqrtl(r.b[l + 1]) * hz[k][l + 1]));
         }
         inner[(size_t)k * H + kp] = acc;
       }
@@ -252,6 +275,14 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
       }
     for (int k = 0; k < H; ++k)
       for (int l = 0; l < Q; ++l) r.HW[(size_t)k * Q + l] = (double)(r.w[k] * hz[k][l]);
+    if (lag) {
+      Rule rh;
+      std::string e2;
+      int st = build_rule(kHalf, Q, 1.0, rh, e2);
+      if (st) { err = "equilibrium rule: " + e2; return st; }
+      r.zm = rh.z;
+      r.wm = rh.w;
+    }
   } else {
     // Eq. (H_Kk) with He_l = sqrt(l!) h_l (orthonormal h_l):
     // He_{l+1}(z_k) He_l(z_k')/l! = sqrt(l+1) h_{l+1}(z_k) h_l(z_k').
@@ -284,8 +315,10 @@ int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
 // so the coefficient G^+_l = int_0^inf dp g h_l(p/p0) of Sec. IV.B.3 is
 //   int_{y0}^inf omega(y) h_l(ub + s y) dy,   ub = m u/p0, s = sqrt(mT)/p0,
 // y0 = -u sqrt(m/T): the part on [0, inf) is a polynomial of degree <= N
-// against the half-range weight, integrated exactly by the Q-point rule
-// itself; the remainder over [y0, 0] is a short Gauss-Legendre integral.
+// against the half-range Gaussian weight, integrated exactly by a Q-point
+// half-range Gauss-Hermite rule (the rule itself for HHLB, an auxiliary one
+// for the Laguerre model); the remainder over [y0, 0] is a short
+// Gauss-Legendre integral.
 // G^-_l follows with u -> -u.  Then g_k = w_k sum_{l<=N} G^sigma_l h_l(z_k).
 // Full range (Sec. IV.A.3): G_l = E[He_l(X)], X ~ N(ub, mT/p0^2), from
 // G_{l+1} = ub G_l + l (mT/p0^2 - 1) G_{l-1}; g_k = w_k sum G_l He_l(z_k)/l!.
@@ -315,11 +348,15 @@ void equilibrium_nc(const Rule &r, int N, ld u, ld T, int nc, ld *g) {
   if (nc > 0) gauss_legendre01(nc, tau, lam);
   ld ub = m * u / p0, s = sqrtl(m * T) / p0, y0 = -u * sqrtl(m / T);
   std::vector<ld> h(Q + 1), Gp(N + 1, 0), Gm(N + 1, 0);
-  for (int j = 0; j < Q; ++j) {
-    ortho_values(r, N, ub + s * r.z[j], h.data());
-    for (int l = 0; l <= N; ++l) Gp[l] += r.w[j] * h[l];
-    ortho_values(r, N, -ub + s * r.z[j], h.data());
-    for (int l = 0; l <= N; ++l) Gm[l] += r.w[j] * h[l];
+  // main part: a half-range Gauss-Hermite rule (the rule itself, or the
+  // auxiliary one of a Laguerre rule)
+  const std::vector<ld> &zr = r.zm.empty() ? r.z : r.zm;
+  const std::vector<ld> &wr = r.wm.empty() ? r.w : r.wm;
+  for (size_t j = 0; j < zr.size(); ++j) {
+    ortho_values(r, N, ub + s * zr[j], h.data());
+    for (int l = 0; l <= N; ++l) Gp[l] += wr[j] * h[l];
+    ortho_values(r, N, -ub + s * zr[j], h.data());
+    for (int l = 0; l <= N; ++l) Gm[l] += wr[j] * h[l];
   }
   if (y0 != 0) {
     for (int i = 0; i < nc; ++i) {
@@ -353,7 +390,7 @@ double correction_limit(const Rule &r, int N, int nc, double tol) {
 
 void correction_limits(const Rule &r, int N, const int *ncs, int n, double tol, double *out) {
   for (int j = 0; j < n; ++j) out[j] = 0.0;
-  if (r.quad != kHalf) return;
+  if (!half_range(r.quad)) return;
   const ld Ts[4] = {0.5L, 1.0L, 2.0L, 3.0L};
   std::vector<ld> g(r.V), gr(r.V);
   std::vector<bool> active(n);
@@ -363,7 +400,12 @@ void correction_limits(const Rule &r, int N, const int *ncs, int n, double tol, 
     n_active += active[j];
   }
   // the grid 1e-6 .. 1 of |y0|; a count keeps the last y0 of an unbroken run
-  // of passes; the 40-point reference is shared by every count
+  // of passes; the 40-point reference is shared by every count.  A count
+  // passes when its difference from the reference is below tol max|g| or
+  // below 8 times the evaluation's own rounding noise (the 40- against the
+  // 48-point reference): an ill-conditioned equilibrium (the Laguerre rule at
+  // the hot end of the range) otherwise fails every count on noise alone.
+  std::vector<ld> g2(r.V);
   for (int e = 0; e <= 96 && n_active > 0; ++e) {
     const ld y = 1e-6L * powl(10.0L, e / 16.0L);
     std::vector<bool> ok(n, true);
@@ -371,14 +413,19 @@ void correction_limits(const Rule &r, int N, const int *ncs, int n, double tol, 
       for (int sgn = -1; sgn <= 1; sgn += 2) {
         const ld u = sgn * y * sqrtl(T);
         equilibrium_nc(r, N, u, T, 40, gr.data());
-        ld mx = 0;
-        for (int k = 0; k < r.V; ++k) mx = std::max(mx, fabsl(gr[k]));
+        equilibrium_nc(r, N, u, T, 48, g2.data());
+        ld mx = 0, noise = 0;
+        for (int k = 0; k < r.V; ++k) {
+          mx = std::max(mx, fabsl(gr[k]));
+          noise = std::max(noise, fabsl(g2[k] - gr[k]));
+        }
+        const ld bound = std::max((ld)tol * mx, 8 * noise);
         for (int j = 0; j < n; ++j) {
           if (!active[j] || !ok[j]) continue;
           equilibrium_nc(r, N, u, T, ncs[j], g.data());
           ld err = 0;
           for (int k = 0; k < r.V; ++k) err = std::max(err, fabsl(g[k] - gr[k]));
-          if (err > tol * mx) ok[j] = false;
+          if (err > bound) ok[j] = false;
         }
       }
     for (int j = 0; j < n; ++j) {

@@ -1,4 +1,5 @@
-// Host-side tables of the half-range / full-range Gauss-Hermite models,
+// Host-side tables of the half-range / full-range Gauss-Hermite and the
+// half-range Gauss-Laguerre models,
 // built in long double and rounded to double once.
 #pragma once
 #include <string>
@@ -6,7 +7,9 @@
 
 namespace hhlb {
 
-constexpr int kHalf = 0, kFull = 1;
+constexpr int kHalf = 0, kFull = 1, kHalfLag = 2;   // half Hermite, full Hermite, half Laguerre
+// half-range kinds share the kernels' split force matrix and equilibrium form
+inline bool half_range(int quad) { return quad != kFull; }
 constexpr int kQmaxTables = 64;   // largest Q the host builder accepts
 
 struct Rule {
@@ -23,6 +26,10 @@ struct Rule {
   std::vector<double> Kin, ka, kb;   // H x H, H, H
   // HW[k][l] = w_k h_l(z_k) (half, H x Q) or w_k He_l(z_k)/l! (full, V x Q)
   std::vector<double> HW;
+  // half-range Laguerre: a Q-point half-range Gauss-Hermite rule for the main
+  // part of the equilibrium coefficients (the Maxwellian becomes the normal
+  // density there, which the Laguerre weight does not integrate exactly)
+  std::vector<long double> zm, wm;
 };
 
 // Builds the rule; returns 0 or a negative hhlb_status and an error text.

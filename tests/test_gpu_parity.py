@@ -77,6 +77,21 @@ def test_q16_weno5():
     _check([ch], 25, perturb=0.02, what="HHLB(15;16)")
 
 
+def test_half_range_laguerre():
+    """Half-range Gauss-Laguerre model (Eqs. wk_half, hh_Kk_L) through the same
+    kernels: Q = 4 upwind-3 (two windows, ragged), Q = 8 WENO-5 on the
+    stretched grid with a perturbed start, Q = 16 WENO-5 (matrix-core path),
+    p0 scaled so the nodes span the thermal range."""
+    h = H()
+    chans = [h.Channel(quad=h.HALF_LAGUERRE, Q=4, Nx=64, adv=h.UPWIND3, transverse_dof=2, Kn=0.1,
+                       g=-0.3, T_left=1.0, T_right=1.4, p0=0.4, dt=-0.5),
+             h.Channel(quad=h.HALF_LAGUERRE, Q=8, Nx=130, adv=h.WENO5, stretch_A=0.9, Kn=0.05,
+                       g=-0.5, T_left=1.0, T_right=2.0, p0=0.3, dt=-0.5),
+             h.Channel(quad=h.HALF_LAGUERRE, Q=16, Nx=121, adv=h.WENO5, stretch_A=0.6, Kn=0.02,
+                       g=-1.0, T_left=1.0, T_right=1.5, p0=0.2, dt=-0.5)]
+    _check(chans, 40, perturb=0.03, what="half-range Laguerre")
+
+
 def test_edge_cases_batch():
     """Minimum Nx = 8 (both walls in one window), collisionless Kn = inf,
     no chi (Dt = 0), N < Q - 1, p0 != 1, positive g, a mixed batch of model

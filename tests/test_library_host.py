@@ -24,8 +24,12 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("quad,Q", [(H.HALF_HERMITE, q) for q in (1, 2, 3, 4, 6, 8, 12, 16)] +
-                         [(H.FULL_HERMITE, q) for q in (2, 4, 8, 16)])
+                         [(H.FULL_HERMITE, q) for q in (2, 4, 8, 16)] +
+                         [(H.HALF_LAGUERRE, q) for q in (1, 2, 3, 4, 6, 8, 12, 16)])
 def test_host_tables_match_oracle(quad, Q):
+    """The library's tables (recurrence, Jacobi eigenvalues, Christoffel
+    weights, force block by integration by parts) against the oracle's
+    (monomial coefficients, bisection, Eq. wk_half, Eq. hh_Kk / hh_Kk_L)."""
     p, w = H.nodes(quad, Q)
     K = H.force_matrix(quad, Q)
     po, wo, Ko, *_ = O.tables(quad, Q)
@@ -42,6 +46,26 @@ def test_host_equilibrium_matches_oracle(quad, Q, u, T):
     g = H.equilibrium(quad, Q, N, 1.3, u, T)
     go = O.equilibrium(quad, Q, N, 1.3, u, T)
     np.testing.assert_allclose(g, go, rtol=0, atol=2e-15 * np.abs(go).max())
+
+
+@pytest.mark.parametrize("Q,N", [(4, 3), (8, 7), (8, 4), (16, 15)])
+@pytest.mark.parametrize("p0", [1.0, 0.3])
+@pytest.mark.parametrize("u,T", [(0.0, 1.0), (0.12, 1.7), (-0.3, 0.6)])
+def test_host_equilibrium_laguerre_matches_oracle(Q, N, p0, u, T):
+    g = H.equilibrium(H.HALF_LAGUERRE, Q, N, 1.3, u, T, p0)
+    go = O.equilibrium(O.LAGUERRE, Q, N, 1.3, u, T, p0)
+    np.testing.assert_allclose(g, go, rtol=0, atol=2e-15 * np.abs(go).max())
+
+
+def test_mixed_forms_reject_laguerre():
+    """The mixed-precision forms are built for the half-range Hermite model."""
+    ch = H.Channel(quad=H.HALF_LAGUERRE, Q=4, p0=0.4)
+    st, h = _create([ch], precision=H.MIXED_F32)
+    assert st == -2
+    assert "Hermite" in H.lib().hhlb_last_error().decode()
+    st, h = _create([ch])
+    assert st == 0
+    assert H.lib().hhlb_destroy(h) == 0
 
 
 def test_host_equilibrium_lower_order():
