@@ -91,6 +91,7 @@ def lib():
         _lib.orc_rhs.argtypes = [ctypes.POINTER(_Channel), dp, dp, dp, dp, dp]
         _lib.orc_run.argtypes = [ctypes.POINTER(_Channel), ctypes.c_long, dp, dp, dp, ctypes.c_int]
         _lib.orc_moments.argtypes = [ctypes.POINTER(_Channel), dp, dp, dp, dp, dp]
+        _lib.orc_set_qmono.argtypes = [ctypes.c_int]
     return _lib
 
 
@@ -110,6 +111,13 @@ def tables(quad: int, Q: int, p0: float = 1.0):
     if r < 0:
         raise ValueError(f"oracle: bad table arguments quad={quad} Q={Q} p0={p0}")
     return p, w, K, Kin, Kd
+
+
+def set_qmono(qmono: int) -> int:
+    """Test-only: half-range Hermite rules with Q > qmono are built from the
+    three-term recurrence instead of monomial coefficients (default 32).
+    Returns the previous value."""
+    return lib().orc_set_qmono(int(qmono))
 
 
 def hh_coeffs(lmax: int) -> np.ndarray:

@@ -36,8 +36,13 @@
 
 typedef __float128 qf;
 
-#define ORC_QMAX 32            /* largest quadrature order the tables accept  */
+#define ORC_QMAX 256           /* largest quadrature order the tables accept  */
 #define ORC_VMAX (2 * ORC_QMAX)
+#define ORC_QMONO 16           /* half-range Hermite: monomial construction up to
+                                  this Q, the three-term recurrence beyond it   */
+#define ORC_QLAG 32            /* largest half-range Laguerre order            */
+#define ORC_CMAX (ORC_QLAG + 2)  /* monomial rows kept: Laguerre l <= Q+1, and
+                                    the recurrence rules' h_0 .. h_21          */
 
 enum { ORC_HALF = 0, ORC_FULL = 1, ORC_HALF_LAGUERRE = 2 };
 enum { ORC_WENO5 = 0, ORC_UPWIND3 = 1 };
@@ -68,8 +73,13 @@ typedef struct {
   double p0;
   qf z[ORC_QMAX];                /* positive nodes z_k (ascending), H of them */
   qf w[ORC_QMAX];                /* their weights                             */
-  /* half-range: monomial coefficients c[l][s] of the orthonormal h_l        */
-  qf c[ORC_QMAX + 2][ORC_QMAX + 2];
+  /* half-range: monomial coefficients c[l][s] of the orthonormal h_l
+   * (l <= Q+1 up to ORC_QMONO; l <= 21, the equilibrium's range, beyond)  */
+  qf c[ORC_CMAX][ORC_CMAX];
+  /* half-range Hermite beyond ORC_QMONO: orthonormal recurrence
+   * sqrt(b_{l+1}) h_{l+1} = (z - a_l) h_l - sqrt(b_l) h_{l-1}, h_0 = 1/sqrt(b_0) */
+  int rec;
+  qf ra[ORC_QMAX + 3], rb[ORC_QMAX + 4];
   /* poly value at the positive nodes: P[l][k] = h_l(z_k) or He_l(z_k)       */
   qf P[ORC_QMAX + 2][ORC_QMAX];
   double p[ORC_VMAX], wd[ORC_VMAX];  /* p_k and w_k over all V nodes (double) */
@@ -99,11 +109,11 @@ static qf hh_inner(const qf *a, int da, const qf *b, int db, const qf *mu) {
  * leading coefficient positive.  c[l][s] is the coefficient of z^s in h_l,
  * i.e. the paper's h_{l,s} of Eq. (phi_expl). */
 static void hh_build_polys(orc_tables *t, int lmax) {
-  qf mu[2 * (ORC_QMAX + 2) + 2];
+  qf mu[2 * ORC_CMAX + 2];
   hh_moments(2 * lmax + 2, mu);
   memset(t->c, 0, sizeof(t->c));
   for (int l = 0; l <= lmax; ++l) {
-    qf v[ORC_QMAX + 2];
+    qf v[ORC_CMAX];
     memset(v, 0, sizeof(v));
     v[l] = 1;
     for (int pass = 0; pass < 2; ++pass)
@@ -169,12 +179,195 @@ static void family_roots(const orc_tables *t, poly_fn f, int n, qf lo_all, qf *r
   for (int j = 0; j < n; ++j) roots[j] = prev[j];
 }
 
+/* ---- half-range Hermite beyond ORC_QMONO: the three-term recurrence ---- */
+
+/* Test-only switch: half-range Hermite rules with Q above this use the
+ * recurrence construction (default ORC_QMONO). */
+static int g_qmono = ORC_QMONO;
+
+/* Gauss-Legendre nodes and weights on [-1, 1] (Newton on the Legendre
+ * recurrence), n points, in __float128. */
+static void gl_nodes(int n, qf *x, qf *w) {
+  for (int i = 0; i < n; ++i) {
+    qf z = cosq(M_PIq * ((qf)i + 0.75Q) / ((qf)n + 0.5Q)), dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      qf p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        qf p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      qf dz = p1 / dp;
+      z -= dz;
+      if (fabsq(dz) < 1e-33Q) break;
+    }
+    x[i] = z;
+    w[i] = 2 / ((1 - z * z) * dp * dp);
+  }
+}
+
+/* Recurrence coefficients of omega(z) = exp(-z^2/2)/sqrt(2 pi) on [0, inf)
+ * by the discretised Stieltjes procedure (orthonormal form): the measure is
+ * replaced by a composite 40-point Gauss-Legendre rule on 110 panels of
+ * width 0.4 over [0, 44] (omega(44) = 1e-421, far below what the rules
+ * resolve).  Returns a_0..a_{n-1}, b_0..b_n (b_0 = int omega). */
+static int hh_stieltjes(int n, qf *a, qf *b) {
+  enum { PAN = 110, PER = 40 };
+  const qf width = 0.4Q;
+  qf gx[PER], gw[PER];
+  gl_nodes(PER, gx, gw);
+  const int M = PAN * PER;
+  qf *x = (qf *)malloc(sizeof(qf) * M), *wt = (qf *)malloc(sizeof(qf) * M);
+  qf *pk = (qf *)malloc(sizeof(qf) * M), *pm = (qf *)calloc(M, sizeof(qf));
+  if (!x || !wt || !pk || !pm) { free(x); free(wt); free(pk); free(pm); return -1; }
+  const qf s2pi = sqrtq(2 * M_PIq);
+  for (int q = 0; q < PAN; ++q)
+    for (int i = 0; i < PER; ++i) {
+      qf z = width * ((qf)q + (gx[i] + 1) / 2);
+      x[q * PER + i] = z;
+      wt[q * PER + i] = gw[i] * width / 2 * expq(-z * z / 2) / s2pi;
+    }
+  qf nrm = 0;
+  for (int j = 0; j < M; ++j) nrm += wt[j];
+  b[0] = nrm;
+  for (int j = 0; j < M; ++j) pk[j] = 1 / sqrtq(nrm);
+  for (int l = 0; l < n; ++l) {
+    qf al = 0;
+    for (int j = 0; j < M; ++j) al += wt[j] * x[j] * pk[j] * pk[j];
+    a[l] = al;
+    qf sb = l == 0 ? 0 : sqrtq(b[l]), nn = 0;
+    for (int j = 0; j < M; ++j) {
+      qf v = (x[j] - al) * pk[j] - sb * pm[j];
+      pm[j] = pk[j];
+      pk[j] = v;
+      nn += wt[j] * v * v;
+    }
+    b[l + 1] = nn;
+    qf inv = 1 / sqrtq(nn);
+    for (int j = 0; j < M; ++j) pk[j] *= inv;
+  }
+  free(x); free(wt); free(pk); free(pm);
+  return 0;
+}
+
+/* h_0(z) .. h_n(z) from the orthonormal recurrence. */
+static void rec_values(const orc_tables *t, int n, qf z, qf *h) {
+  h[0] = 1 / sqrtq(t->rb[0]);
+  if (n >= 1) h[1] = (z - t->ra[0]) * h[0] / sqrtq(t->rb[1]);
+  for (int l = 1; l < n; ++l) h[l + 1] = ((z - t->ra[l]) * h[l] - sqrtq(t->rb[l]) * h[l - 1]) / sqrtq(t->rb[l + 1]);
+}
+
+/* Roots of h_Q: the eigenvalues of the Q x Q Jacobi matrix (diagonal a_l,
+ * off-diagonal sqrt(b_l)) by Sturm-sequence bisection. */
+static void sturm_roots(const orc_tables *t, int Q, qf lo, qf hi, qf *roots) {
+  for (int k = 0; k < Q; ++k) {
+    qf a = lo, b = hi;
+    for (int it = 0; it < 240; ++it) {
+      qf m = (a + b) / 2;
+      if (m <= a || m >= b) break;
+      int cnt = 0;
+      qf d = 1;
+      for (int i = 0; i < Q; ++i) {
+        qf dn = (t->ra[i] - m) - (i == 0 ? 0 : t->rb[i] / d);
+        if (dn == 0) dn = -1e-4900Q;
+        if (dn < 0) ++cnt;
+        d = dn;
+      }
+      if (cnt > k) b = m; else a = m;
+    }
+    roots[k] = (a + b) / 2;
+  }
+}
+
+/* Half-range Gauss-Hermite rule and force matrix from the recurrence: the
+ * same Sec. IV.B.1 rule and Eq. (hh_Kk_hh) matrix as build_half, with
+ * h_{l,0} = h_l(0) and h_{l,l}/h_{l+1,l+1} = sqrt(b_{l+1}) read off the
+ * recurrence.  Weights by the general Eq. (wk_half_gen),
+ * w_k = -a_Q gamma_Q / (h_{Q+1}(z_k) h_Q'(z_k)) with gamma_Q = 1 and h_Q'
+ * from the differentiated recurrence: at Q = 200 the specialised
+ * Eq. (wk_half) evaluated through the same recurrence loses 1e-12 (its
+ * weights sum to 0.4999999999997), the general form keeps 1e-32.  The
+ * equilibrium (N <= 20 here) keeps the monomial coefficients of h_0 .. h_21. */
+static int build_half_rec(orc_tables *t, int Q, double p0) {
+  t->quad = ORC_HALF; t->Q = Q; t->V = 2 * Q; t->H = Q; t->p0 = p0; t->rec = 1;
+  if (hh_stieltjes(Q + 2, t->ra, t->rb)) return -1;
+  hh_build_polys(t, 21);
+  qf r[ORC_QMAX + 2];
+  sturm_roots(t, Q, 0, 4.0Q + 3.0Q * sqrtq((qf)Q), r);
+  const qf s2pi = sqrtq(2.0Q * M_PIq);
+  qf h0[ORC_QMAX + 3], hv[ORC_QMAX + 3];
+  rec_values(t, Q + 1, 0, h0);
+  const qf aQ = 1 / sqrtq(t->rb[Q + 1]);
+  for (int k = 0; k < Q; ++k) {
+    const qf z = r[k];
+    t->z[k] = z;
+    rec_values(t, Q + 1, z, hv);
+    /* h_l'(z): differentiate sqrt(b_{l+1}) h_{l+1} = (z - a_l) h_l - sqrt(b_l) h_{l-1} */
+    qf dm = 0, dc = 1 / sqrtq(t->rb[1]) * hv[0];   /* h_0', h_1' */
+    for (int l = 1; l < Q; ++l) {
+      qf dn = ((z - t->ra[l]) * dc + hv[l] - sqrtq(t->rb[l]) * dm) / sqrtq(t->rb[l + 1]);
+      dm = dc;
+      dc = dn;
+    }
+    t->w[k] = -aQ / (hv[Q + 1] * dc);   /* dc = h_Q'(z_k) */
+    for (int l = 0; l <= Q + 1; ++l) t->P[l][k] = hv[l];
+  }
+  const int V = 2 * Q;
+  for (int k = 0; k < V; ++k) {
+    int kk = k % Q;
+    t->p[k] = (double)((k < Q ? 1 : -1) * (qf)p0 * t->z[kk]);
+    t->wd[k] = (double)t->w[kk];
+  }
+  qf *Phi0 = (qf *)malloc(sizeof(qf) * Q), *tail = (qf *)malloc(sizeof(qf) * (size_t)Q * Q);
+  qf *inner = (qf *)malloc(sizeof(qf) * (size_t)Q * Q);
+  if (!Phi0 || !tail || !inner) { free(Phi0); free(tail); free(inner); return -1; }
+  for (int k = 0; k < Q; ++k) {
+    qf acc = 0;
+    for (int s = 0; s < Q; ++s) acc += h0[s] * t->P[s][k];
+    Phi0[k] = acc;
+    /* tail[l][k] = sum_{s=l+1}^{Q-1} h_s(0) h_s(z_k) */
+    qf tl = 0;
+    for (int l = Q - 1; l >= 0; --l) {
+      tail[(size_t)l * Q + k] = tl;
+      tl += h0[l] * t->P[l][k];
+    }
+  }
+  for (int k = 0; k < Q; ++k)
+    for (int kq = 0; kq < Q; ++kq) {
+      qf acc = 0;
+      for (int l = 0; l <= Q - 2; ++l) {
+        qf br = h0[l] / s2pi * tail[(size_t)l * Q + k] - sqrtq(t->rb[l + 1]) * t->P[l + 1][k];
+        acc += t->P[l][kq] * br;
+      }
+      inner[(size_t)k * Q + kq] = acc;
+    }
+  for (int k = 0; k < V; ++k) {
+    int kk = k % Q;
+    qf sk = (k < Q) ? 1 : -1;
+    for (int kp = 0; kp < V; ++kp) {
+      int kq = kp % Q;
+      qf skp = (kp < Q) ? 1 : -1;
+      qf pref = t->w[kk] * sk / (qf)p0;
+      qf within = pref * (1 + sk * skp) / 2 * inner[(size_t)kk * Q + kq];
+      qf cross = -pref * Phi0[kk] * Phi0[kq] / (2 * s2pi);
+      qf delta = pref * sk * skp * Phi0[kk] * Phi0[kq] / (2 * s2pi);
+      t->Kin[(size_t)k * V + kp] = (double)within;
+      t->Kd[(size_t)k * V + kp] = (double)delta;
+      t->K[(size_t)k * V + kp] = (double)(within + cross);
+    }
+  }
+  free(Phi0); free(tail); free(inner);
+  return 0;
+}
+
 /* Half-range Gauss-Hermite rule and force matrix.
  * Nodes: the Q positive roots of h_Q (Sec. IV.B.1).
  * Weights: Eq. (wk_half), w_k = z_k a_Q^2 / (h_{Q+1}(z_k)^2 [z_k + h_{Q,0}^2/sqrt(2 pi)]),
  *          a_Q = h_{Q+1,Q+1}/h_{Q,Q} (Eq. a_def).
  * Force matrix: Eq. (hh_Kk_hh) with Phi^Q_0 of Eq. (Phi_def_hh). */
 static int build_half(orc_tables *t, int Q, double p0) {
+  if (Q > g_qmono) return build_half_rec(t, Q, p0);
   t->quad = ORC_HALF; t->Q = Q; t->V = 2 * Q; t->H = Q; t->p0 = p0;
   hh_build_polys(t, Q + 1);
   qf r[ORC_QMAX + 2];
@@ -345,6 +538,10 @@ static int build_full(orc_tables *t, int Q, double p0) {
 static int build_tables(orc_tables *t, int quad, int Q, double p0) {
   memset(t, 0, sizeof(*t));
   if (Q < 1 || Q > ORC_QMAX || !(p0 > 0)) return -1;
+  /* monomial constructions (Laguerre, and Hermite up to the switch) hold
+   * c[l][s] up to l = Q + 1; the full-range roots cost O(Q^3) */
+  if (quad == ORC_HALF_LAGUERRE && Q > ORC_QLAG) return -1;
+  if (quad == ORC_FULL && Q > 64) return -1;
   if (quad == ORC_HALF) return build_half(t, Q, p0);
   if (quad == ORC_FULL) return build_full(t, Q, p0);
   if (quad == ORC_HALF_LAGUERRE) return build_half_laguerre(t, Q, p0);
@@ -652,6 +849,7 @@ static int ctx_init(orc_ctx *c, const orc_channel *ch) {
   if (ch->Dt != 0 && ch->Dt != 2) return -1;
   if (ch->adv != ORC_WENO5 && ch->adv != ORC_UPWIND3) return -1;
   if (build_tables(&c->t, ch->quad, ch->Q, ch->p0)) return -1;
+  if (c->t.rec && ch->N > 20) return -1;   /* recurrence rules keep h_0..h_21 in monomials */
   c->V = c->t.V; c->H = c->t.H; c->N = ch->N; c->Nx = ch->Nx; c->Ne = ch->Nx + 6;
   c->xf = (double *)malloc(sizeof(double) * (ch->Nx + 1));
   c->dx = (double *)malloc(sizeof(double) * ch->Nx);
@@ -690,7 +888,7 @@ int orc_tables_get(int quad, int Q, double p0, double *p, double *w, double *K,
 /* Monomial coefficients of the orthonormal half-range Hermite polynomials
  * h_0 .. h_lmax, row l holding h_{l,0..l} (out: (lmax+1)^2, row stride lmax+1). */
 int orc_hh_coeffs(int lmax, double *out) {
-  if (lmax < 0 || lmax > ORC_QMAX + 1) return -1;
+  if (lmax < 0 || lmax > ORC_CMAX - 1) return -1;
   orc_tables *t = (orc_tables *)malloc(sizeof(orc_tables));
   memset(t, 0, sizeof(*t));
   hh_build_polys(t, lmax);
@@ -700,11 +898,20 @@ int orc_hh_coeffs(int lmax, double *out) {
   return 0;
 }
 
+/* Test-only: half-range Hermite rules with Q above qmono (clamped to
+ * 0 .. ORC_QMONO) are built from the recurrence; returns the previous value.
+ * Lets the tests compare both constructions where both apply. */
+int orc_set_qmono(int qmono) {
+  int old = g_qmono;
+  g_qmono = qmono < 0 ? 0 : (qmono > ORC_QMONO ? ORC_QMONO : qmono);
+  return old;
+}
+
 /* Discrete equilibrium f^eq_k = n g_k(u, T) of order N (V values). */
 int orc_equilibrium(int quad, int Q, int N, double p0, double n, double u, double T, double *feq) {
   if (N < 0 || N >= Q || !(T > 0)) return -1;
   orc_tables *t = (orc_tables *)malloc(sizeof(orc_tables));
-  if (build_tables(t, quad, Q, p0)) { free(t); return -1; }
+  if (build_tables(t, quad, Q, p0) || (t->rec && N > 20)) { free(t); return -1; }
   equilibrium(t, N, u, T, feq);
   for (int k = 0; k < t->V; ++k) feq[k] *= n;
   int V = t->V;
@@ -729,9 +936,10 @@ int orc_grid(const orc_channel *ch, double *xf, double *dx, double *xc) {
  * when Dt = 0); Lf, Lc likewise.  nw[2] receives the wall densities. */
 int orc_rhs(const orc_channel *ch, const double *f, const double *chi, double *Lf, double *Lc,
             double *nw) {
-  orc_ctx c;
-  if (ctx_init(&c, ch)) return -1;
-  int V = c.V, Nx = c.Nx, Ne = c.Ne;
+  orc_ctx *c = (orc_ctx *)malloc(sizeof(orc_ctx));   /* the tables are large: heap, not stack */
+  if (!c) return -1;
+  if (ctx_init(c, ch)) { ctx_free(c); free(c); return -1; }
+  int V = c->V, Nx = c->Nx, Ne = c->Ne;
   double *ye = (double *)calloc((size_t)2 * V * Ne, sizeof(double));
   double *Lct = (double *)calloc((size_t)V * Nx, sizeof(double));
   for (int k = 0; k < V; ++k)
@@ -739,10 +947,11 @@ int orc_rhs(const orc_channel *ch, const double *f, const double *chi, double *L
       ye[(size_t)k * Ne + EX(i)] = f[(size_t)k * Nx + i - 1];
       if (ch->Dt > 0) ye[(size_t)(V + k) * Ne + EX(i)] = chi[(size_t)k * Nx + i - 1];
     }
-  rhs(&c, ye, Lf, Lct, nw);
+  rhs(c, ye, Lf, Lct, nw);
   if (ch->Dt > 0 && Lc) memcpy(Lc, Lct, sizeof(double) * V * Nx);
   free(ye); free(Lct);
-  ctx_free(&c);
+  ctx_free(c);
+  free(c);
   return 0;
 }
 
@@ -754,10 +963,11 @@ int orc_rhs(const orc_channel *ch, const double *f, const double *chi, double *L
  * of the force matrix: a planted mistake used only by the negative control
  * test of the mass-bias argument of Sec. I. */
 int orc_run(const orc_channel *ch, long nsteps, double *f, double *chi, double *nw, int drop_delta) {
-  orc_ctx c;
-  if (ctx_init(&c, ch)) return -1;
-  c.drop_delta = drop_delta;
-  const int V = c.V, Nx = c.Nx, Ne = c.Ne;
+  orc_ctx *c = (orc_ctx *)malloc(sizeof(orc_ctx));   /* the tables are large: heap, not stack */
+  if (!c) return -1;
+  if (ctx_init(c, ch)) { ctx_free(c); free(c); return -1; }
+  c->drop_delta = drop_delta;
+  const int V = c->V, Nx = c->Nx, Ne = c->Ne;
   const int nfun = ch->Dt > 0 ? 2 : 1;
   const double dt = ch->dt;
   size_t ns = (size_t)V * Nx;
@@ -776,7 +986,7 @@ int orc_run(const orc_channel *ch, long nsteps, double *f, double *chi, double *
           for (int i = 1; i <= Nx; ++i)
             ye[(size_t)(fn * V + k) * Ne + EX(i)] = ys[fn * ns + (size_t)k * Nx + i - 1];
       memset(L, 0, sizeof(double) * 2 * ns);
-      rhs(&c, ye, L, L + ns, nwl);
+      rhs(c, ye, L, L + ns, nwl);
       for (size_t j = 0; j < (size_t)nfun * ns; ++j) {
         double y = y0[j], s = ys[j], l = L[j];
         if (stage == 0) ys[j] = y + dt * l;
@@ -790,7 +1000,8 @@ int orc_run(const orc_channel *ch, long nsteps, double *f, double *chi, double *
   if (nfun > 1) memcpy(chi, y0 + ns, sizeof(double) * ns);
   if (nw) { nw[0] = nwl[0]; nw[1] = nwl[1]; }
   free(y0); free(ys); free(L); free(ye);
-  ctx_free(&c);
+  ctx_free(c);
+  free(c);
   return 0;
 }
 
