@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/hhlb.h"
+#include "large_kernels.hpp"
 #include "launch.hpp"
 #include "step_kernels.hpp"
 #include "tables.hpp"
@@ -240,6 +241,11 @@ struct ModelClass {
   Launcher launch4 = nullptr;   // four waves per window (FP64, f and chi), if built
   std::vector<hhlb::DevWindow> windows;
   size_t win_off = 0;  // byte offset in workspace
+  // Q > 16 (half-range Hermite, FP64): the node-parallel stage, whose tables
+  // (DevLarge, then KinT and HWs) live in their own workspace block
+  bool large = false;
+  std::vector<char> lblob;
+  size_t lbl_off = 0;
 };
 
 struct hhlb_solver {
@@ -259,6 +265,9 @@ struct hhlb_solver {
   // workspace layout (byte offsets)
   size_t o_tables = 0, o_chans = 0, o_chclass = 0, o_V = 0, o_dx = 0, o_invdx = 0, o_gw = 0,
          o_nwall = 0, o_feq = 0, o_feqoff = 0, o_flag = 0, o_state = 0, bytes = 0;
+  // large classes: per-cell output of the cell phase and the stage's wall densities
+  size_t o_cell = 0, o_lnw = 0;
+  bool any_large = false;
   char *ws = nullptr;
   // stored state.  FP64 form: hi[0] = y^n (the last stage updates it in
   // place), B and C = RK stage values.  Mixed form: hi[par] + lo[par] = y^n
@@ -495,6 +504,62 @@ hhlb_status cached_tables(const hhlb_channel &h, int N, int precision, const hhl
   return HHLB_OK;
 }
 
+// Tables of a large half-range class (Q > 16): the momenta in DevTables
+// (the aux kernels read them there) and the node-parallel stage's block.
+hhlb_status make_large_tables(const hhlb_channel &h, int N, const hhlb::Rule &r, hhlb::DevTables &d,
+                              std::vector<char> &blob) {
+  std::memset(&d, 0, sizeof(d));
+  for (int k = 0; k < r.V; ++k) d.p[k] = r.p[k];
+  d.inv_p0 = 1.0 / h.p0;
+  const int H = r.H, Q = h.Q;
+  const size_t nK = (size_t)H * H, nW = (size_t)H * (N + 1);
+  blob.assign(sizeof(hhlb::DevLarge) + sizeof(double) * (nK + nW), 0);
+  hhlb::DevLarge &L = *(hhlb::DevLarge *)blob.data();
+  double *KinT = (double *)(blob.data() + sizeof(hhlb::DevLarge));
+  double *HWs = KinT + nK;
+  L.H = H;
+  L.N = N;
+  L.inv_p0 = 1.0 / h.p0;
+  for (int k = 0; k < H; ++k) { L.ka[k] = r.ka[k]; L.kb[k] = r.kb[k]; }
+  for (int l = 0; l <= N + 1 && l < (int)r.a.size(); ++l) { L.a[l] = (double)r.a[l]; L.mb[l] = (double)r.b[l]; }
+  for (int j = 0; j < H; ++j)
+    for (int k = 0; k < H; ++k) KinT[(size_t)j * H + k] = r.Kin[(size_t)k * H + j];
+  // monic recurrence: the normalisation 1/sqrt(b_0 .. b_l) folds into HWs
+  long double prod = 1;
+  std::vector<long double> inv_norm(N + 1);
+  for (int l = 0; l <= N; ++l) { prod *= r.b[l]; inv_norm[l] = 1.0L / sqrtl(prod); }
+  for (int k = 0; k < H; ++k)
+    for (int l = 0; l <= N; ++l) HWs[(size_t)k * (N + 1) + l] = (double)((long double)r.HW[(size_t)k * Q + l] * inv_norm[l]);
+  // main rule of the equilibrium integral: M = ceil((N+1)/2) half-range points
+  const int M = (N + 2) / 2;
+  hhlb::Rule rm;
+  std::string err2;
+  int st2 = hhlb::build_rule(HHLB_HALF_HERMITE, M, 1.0, rm, err2);
+  if (st2) return fail(st2, "equilibrium rule: " + err2);
+  L.nm = M;
+  for (int j = 0; j < M; ++j) { L.zm[j] = (double)rm.z[j]; L.wm[j] = (double)rm.w[j]; }
+  const int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
+  double limits[hhlb::kLadder] = {0};
+  hhlb::correction_limits(r, N, counts, hhlb::kLadder, 3e-16, limits);
+  const long double inv_s2pi = 1.0L / sqrtl(2 * 3.141592653589793238462643383279502884L);
+  int o = 0;
+  for (int j = 0; j < hhlb::kLadder; ++j) {
+    L.lad_n[j] = counts[j];
+    L.lad_off[j] = o;
+    L.lad_y[j] = limits[j];
+    if (counts[j] > 0) {
+      std::vector<long double> t2, l2;
+      hhlb::gauss_legendre01(counts[j], t2, l2);
+      for (int q = 0; q < counts[j]; ++q) {
+        L.ltau[o + q] = (double)t2[q];
+        L.llamw[o + q] = (double)(l2[q] * inv_s2pi);
+      }
+    }
+    o += counts[j];
+  }
+  return HHLB_OK;
+}
+
 // Kernel launch arguments shared by the aux kernels.
 struct AuxArgs {
   const hhlb::DevTables *tbs;
@@ -614,20 +679,37 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
         ModelClass mc;
         mc.quad = h.quad; mc.Q = h.Q; mc.N = N; mc.adv = h.adv; mc.Dt = h.transverse_dof; mc.p0 = h.p0;
         std::string err;
+        const bool large = h.Q > hhlb::kQmaxDev;
+        if (large) {
+          // the node-parallel stage: half-range Gauss-Hermite, FP64, N <= 20
+          if (h.quad != HHLB_HALF_HERMITE || precision != HHLB_FP64 || N > hhlb::kNmaxLarge ||
+              h.Q > hhlb::kQmaxLarge)
+            return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) + ": Q > " +
+                                                std::to_string(hhlb::kQmaxDev) +
+                                                " runs the half-range Hermite model in FP64 with N <= 20 and Q <= " +
+                                                std::to_string(hhlb::kQmaxLarge));
+        }
         int st = hhlb::build_rule(h.quad, h.Q, h.p0, mc.rule, err);
         if (st) return fail(st, "channel " + std::to_string(c) + ": " + err);
         const int nf = h.transverse_dof > 0 ? 2 : 1;
-        // both half-range kinds run the half-range kernels (tables differ)
-        const int kq = hhlb::half_range(h.quad) ? HHLB_HALF_HERMITE : HHLB_FULL_HERMITE;
-        auto lk = launchers().find({kq, h.Q, nf, h.adv, precision, 2});
-        if (lk == launchers().end())
-          return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) + ": no kernel for quad=" +
-                                              std::to_string(h.quad) + " Q=" + std::to_string(h.Q));
-        mc.launch = lk->second;
-        auto lk4 = launchers().find({kq, h.Q, nf, h.adv, precision, 4});
-        if (lk4 != launchers().end()) mc.launch4 = lk4->second;
-        st = cached_tables(h, N, precision, mc.rule, mc.dev);
-        if (st) return st;
+        if (large) {
+          mc.large = true;
+          s->any_large = true;
+          st = make_large_tables(h, N, mc.rule, mc.dev, mc.lblob);
+          if (st) return st;
+        } else {
+          // both half-range kinds run the half-range kernels (tables differ)
+          const int kq = hhlb::half_range(h.quad) ? HHLB_HALF_HERMITE : HHLB_FULL_HERMITE;
+          auto lk = launchers().find({kq, h.Q, nf, h.adv, precision, 2});
+          if (lk == launchers().end())
+            return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) + ": no kernel for quad=" +
+                                                std::to_string(h.quad) + " Q=" + std::to_string(h.Q));
+          mc.launch = lk->second;
+          auto lk4 = launchers().find({kq, h.Q, nf, h.adv, precision, 4});
+          if (lk4 != launchers().end()) mc.launch4 = lk4->second;
+          st = cached_tables(h, N, precision, mc.rule, mc.dev);
+          if (st) return st;
+        }
         id = (int)s->classes.size();
         s->classes.push_back(std::move(mc));
         cls[key] = id;
@@ -711,6 +793,12 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
     s->o_feq = take(sizeof(double) * feq_total);
     s->o_feqoff = take(sizeof(int32_t) * n_ch);
     s->o_flag = take(sizeof(int32_t));
+    for (auto &mc : s->classes)
+      if (mc.large) mc.lbl_off = take(mc.lblob.size());
+    if (s->any_large) {
+      s->o_cell = take(sizeof(double) * hhlb::kCellStride * s->total_cells);
+      s->o_lnw = take(sizeof(double) * 2 * n_ch);
+    }
     s->o_state = o;
     // per function: FP64 form 3 copies of 8 bytes; mixed form 4 copies of
     // 4 bytes (hi x 2, B, C) and 2 copies of 2 bytes (lo x 2)
@@ -751,9 +839,12 @@ hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr) {
                          hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(ws + s->o_V, s->Vs.data(), sizeof(int32_t) * n_ch, hipMemcpyHostToDevice,
                          s->stream));
-  for (auto &mc : s->classes)
+  for (auto &mc : s->classes) {
     HIP_TRY(hipMemcpyAsync(ws + mc.win_off, mc.windows.data(), sizeof(hhlb::DevWindow) * mc.windows.size(),
                            hipMemcpyHostToDevice, s->stream));
+    if (mc.large)
+      HIP_TRY(hipMemcpyAsync(ws + mc.lbl_off, mc.lblob.data(), mc.lblob.size(), hipMemcpyHostToDevice, s->stream));
+  }
   HIP_TRY(hipMemcpyAsync(ws + s->o_dx, s->dx.data(), sizeof(double) * s->total_cells,
                          hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(ws + s->o_invdx, s->inv_dx.data(), sizeof(double) * s->total_cells,
@@ -873,6 +964,30 @@ void enqueue_class_stage(hhlb_solver *s, size_t ci, int stage, const void *inf, 
                          const int16_t *lo_in_f = nullptr, const int16_t *lo_in_c = nullptr,
                          int16_t *lo_out_f = nullptr, int16_t *lo_out_c = nullptr) {
   ModelClass &mc = s->classes[ci];
+  if (mc.large) {
+    hhlb::LargeArgs la;
+    la.tl = (const hhlb::DevLarge *)(s->ws + mc.lbl_off);
+    la.KinT = (const double *)(s->ws + mc.lbl_off + sizeof(hhlb::DevLarge));
+    la.HWs = la.KinT + (size_t)mc.rule.H * mc.rule.H;
+    la.p = ((const hhlb::DevTables *)(s->ws + s->o_tables) + ci)->p;
+    la.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
+    la.wins = (const hhlb::DevWindow *)(s->ws + mc.win_off);
+    la.nwin = (int32_t)mc.windows.size();
+    la.stage = stage;
+    la.inv_dx = (const double *)(s->ws + s->o_invdx);
+    la.gw = (const double *)(s->ws + s->o_gw);
+    la.in_f = (const double *)inf; la.in_c = (const double *)inc;
+    la.base_f = (const double *)s->fA(); la.base_c = (const double *)s->cA();
+    la.out_f = (double *)outf; la.out_c = (double *)outc;
+    la.a_base = a_base;
+    la.b_stage = b_stage;
+    la.cell = (double *)(s->ws + s->o_cell);
+    la.lnw = (double *)(s->ws + s->o_lnw);
+    la.nwall = (double *)(s->ws + s->o_nwall);
+    la.nfun = mc.Dt > 0 ? 2 : 1;
+    hhlb::launch_large(la, mc.adv, mc.rule.H, stream);
+    return;
+  }
   hhlb::StageArgs a;
   a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables) + ci;
   a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
@@ -1209,7 +1324,11 @@ hhlb_status hhlb_diagnostics(hhlb_solver *s, double *n_wall_dev, double *mass_de
 
 hhlb_status hhlb_launch_info(const hhlb_solver *s, int32_t *launches_per_stage, int64_t *windows_total) {
   if (!s) return fail(HHLB_E_ARG, "null solver");
-  if (launches_per_stage) *launches_per_stage = (int32_t)s->classes.size();
+  if (launches_per_stage) {
+    int32_t n = 0;
+    for (auto &mc : s->classes) n += mc.large ? 2 : 1;   // large classes: cell and node phase
+    *launches_per_stage = n;
+  }
   if (windows_total) {
     int64_t t = 0;
     for (auto &mc : s->classes) t += (int64_t)mc.windows.size();

@@ -1,0 +1,289 @@
+// Node-parallel FP64 stage of the half-range model for large velocity sets
+// (17 <= Q <= 256 nodes per half, equilibrium order N <= 20): the paper's
+// HHLB(20;Q) models of the ballistic study (Sec. VI.D).  A lane holds one
+// cell, as in stage_kernel_half, but the Q nodes of a half no longer fit a
+// lane's registers, so one stage runs as two kernels:
+//   large_cell_kernel: per cell, the moments (Eq. fmoms), 1/tau, the rank-1
+//     force projections and the half-range equilibrium coefficients of both
+//     halves (Sec. IV.B.3, the change of variables of stage_kernel_half);
+//     per channel, the wall densities (Eq. nplus_def).
+//   large_node_kernel: per window and group of NG nodes of one half, the
+//     wall ghosts (Sec. IV.C.3), the force -F (K y)_k with the within-half
+//     block read from a transposed table (Eq. hh_Kk_hh), BGK towards the
+//     synthesised equilibrium, WENO-5 / upwind-3 advection (the lane-parallel
+//     face values of stage_kernel_half) and the RK-3 combination.
+#pragma once
+#include "step_kernels.hpp"
+
+namespace hhlb {
+
+constexpr int kQmaxLarge = 256;   // nodes per half
+constexpr int kNmaxLarge = 20;    // equilibrium order
+constexpr int kCellStride = 48;   // doubles per cell in the cell-phase output
+constexpr int kLargeNG = 8;       // nodes per block of the node phase
+
+// Tables of one large model class.  The transposed within-half block
+// KinT[j * H + k] = Kin[k][j] and HWs[k * (N+1) + l] follow the struct.
+struct DevLarge {
+  int32_t H, N, nm, pad;
+  double inv_p0;
+  double ka[kQmaxLarge], kb[kQmaxLarge];
+  double a[kNmaxLarge + 2], mb[kNmaxLarge + 2];   // monic recurrence
+  double zm[kQmaxDev], wm[kQmaxDev];               // main rule (half-range Gauss-Hermite)
+  int32_t lad_n[kLadder], lad_off[kLadder];
+  double lad_y[kLadder];
+  double ltau[kLadderPts], llamw[kLadderPts];
+};
+
+struct LargeArgs {
+  const DevLarge *tl;
+  const double *KinT, *HWs, *p;   // p: V momenta
+  const DevChannel *chans;
+  const DevWindow *wins;
+  int32_t nwin, stage;
+  const double *inv_dx, *gw;
+  const double *in_f, *in_c;      // stage state
+  const double *base_f, *base_c;  // y^n
+  double *out_f, *out_c;
+  double a_base, b_stage;
+  double *cell;                   // cell-phase output, kCellStride per cell
+  double *lnw;                    // wall densities of this stage, 2 per channel
+  double *nwall;                  // diagnostics copy (written in stage 2)
+  int32_t nfun;
+};
+
+// Cell phase.  Wave 0: lane = cell of the window (lanes 0..kWin-1).  Wave 1:
+// the left-wall density if the window holds cell 0; wave 2: the right-wall
+// density if it holds cell Nx-1 (lanes over the incoming nodes).
+template <int ADV>
+__global__ __launch_bounds__(192) void large_cell_kernel(LargeArgs A) {
+  const DevWindow win = A.wins[blockIdx.x];
+  const DevChannel C = A.chans[win.ch];
+  const DevLarge *tl = A.tl;
+  const int H = tl->H, V = 2 * H, N = tl->N, Nx = C.Nx;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double *yf = A.in_f + C.off, *yc = A.nfun > 1 ? A.in_c + C.off : nullptr;
+  if (wave == 0) {
+    const int i = win.i0 + lane;
+    const bool act = lane < kWin && i < Nx;
+    const int ic = act ? i : Nx - 1;
+    double n = 0, mom = 0, s2 = 0, ech = 0, bf = 0, bc = 0;
+    for (int k = 0; k < V; ++k) {
+      const double v = A.p[k], y = yf[(int64_t)k * Nx + ic], kbv = tl->kb[k < H ? k : k - H];
+      n += y;
+      mom += v * y;
+      s2 += v * v * y;
+      bf += kbv * y;
+      if (yc) {
+        const double x = yc[(int64_t)k * Nx + ic];
+        ech += x;
+        bc += kbv * x;
+      }
+    }
+    const double u = mom / n;
+    const double T = (s2 - u * mom + 2.0 * ech) * C.inv_1pDt / n;
+    double *out = A.cell + (int64_t)(C.cell_off + ic) * kCellStride;
+    double Gp[kNmaxLarge + 1], Gm[kNmaxLarge + 1];
+#pragma unroll
+    for (int l = 0; l <= kNmaxLarge; ++l) Gp[l] = Gm[l] = 0.0;
+    if (C.inv_Kn != 0.0) {
+      const double sT = sqrt(T), s = sT * tl->inv_p0, y0 = -u / sT;
+      auto accum = [&](double *G, double x, double wt) {
+        double qm = 1.0, q = x - tl->a[0];
+        G[0] += wt;
+        if (N >= 1) G[1] += wt * q;
+#pragma unroll
+        for (int l = 1; l < kNmaxLarge; ++l) {
+          if (l + 1 > N) break;
+          const double qn = (x - tl->a[l]) * q - tl->mb[l] * qm;
+          qm = q;
+          q = qn;
+          G[l + 1] += wt * q;
+        }
+      };
+      for (int j = 0; j < tl->nm; ++j) {
+        accum(Gp, u * tl->inv_p0 + s * tl->zm[j], tl->wm[j]);
+        accum(Gm, -u * tl->inv_p0 + s * tl->zm[j], tl->wm[j]);
+      }
+      const double ymax = wave_max(act ? fabs(y0) : 0.0);
+      if (ymax > 0.0) {
+        int li = kLadder - 1;
+        for (int j = 1; j < kLadder; ++j)
+          if (tl->lad_y[j] >= ymax) { li = j; break; }
+        const int nc = tl->lad_n[li], o = tl->lad_off[li];
+        for (int j = 0; j < nc; ++j) {
+          const double t = tl->ltau[o + j], yt = y0 * t;
+          const double e = y0 * tl->llamw[o + j] * exp(-0.5 * yt * yt);
+          accum(Gp, u * tl->inv_p0 * (1.0 - t), -e);
+          accum(Gm, -u * tl->inv_p0 * (1.0 - t), e);
+        }
+      }
+    }
+    if (act) {
+      out[0] = n;
+      out[1] = T;
+      out[2] = n * C.inv_Kn;
+      out[3] = bf;
+      out[4] = bc;
+#pragma unroll
+      for (int l = 0; l <= kNmaxLarge; ++l) {
+        if (l > N) break;
+        out[5 + l] = Gp[l];
+        out[5 + kNmaxLarge + 1 + l] = Gm[l];
+      }
+    }
+    return;
+  }
+  // wall densities from the incoming wall-face fluxes of f (Eq. nplus_def):
+  // ghosts extrapolated quadratically from the three nearest cells
+  const bool left = wave == 1;
+  if (left ? win.i0 != 0 : !(win.i0 <= Nx - 1 && Nx - 1 < win.i0 + kWin)) return;
+  double acc = 0.0;
+  for (int j = lane; j < H; j += 64) {
+    const int k = left ? H + j : j;
+    const double *row = yf + (int64_t)k * Nx;
+    const double y0 = left ? row[0] : row[Nx - 1], y1 = left ? row[1] : row[Nx - 2],
+                 y2 = left ? row[2] : row[Nx - 3];
+    const double g1 = 3.0 * y0 - 3.0 * y1 + y2, g2 = 6.0 * y0 - 8.0 * y1 + 3.0 * y2;
+    acc += A.p[k] * face_value<ADV>(y2, y1, y0, g1, g2);
+  }
+  const double nw = -wave_sum(acc) * (left ? C.inv_DL : C.inv_DR);
+  if (lane == 0) {
+    A.lnw[2 * win.ch + (left ? 0 : 1)] = nw;
+    if (A.stage == 2 && A.nwall) A.nwall[2 * win.ch + (left ? 0 : 1)] = nw;
+  }
+}
+
+// Node phase: blockIdx.x = window, blockIdx.y = group of up to NG nodes of one
+// half (groups never straddle the halves).  One wave; lane = cell
+// i0 - kHalo + lane, as in stage_kernel_half.
+template <int ADV, int NG>
+__global__ __launch_bounds__(64) void large_node_kernel(LargeArgs A) {
+  const DevWindow win = A.wins[blockIdx.x];
+  const DevChannel C = A.chans[win.ch];
+  const DevLarge *tl = A.tl;
+  const int H = tl->H, N = tl->N, Nx = C.Nx;
+  const int gph = (H + NG - 1) / NG;
+  const int hw = blockIdx.y / gph;                 // 0: p > 0, 1: p < 0
+  const int k0 = (blockIdx.y % gph) * NG;          // first node within the half
+  const int ng = H - k0 < NG ? H - k0 : NG;
+  const int lane = threadIdx.x;
+  const int i = win.i0 - kHalo + lane;
+  const bool inside = i >= 0 && i < Nx;
+  const int ic = inside ? i : (i < 0 ? 0 : Nx - 1);   // clamped: loads stay in bounds
+  const bool nfc = A.nfun > 1;
+  const double sg = hw ? -1.0 : 1.0;
+  const int64_t rowh = C.off + (int64_t)hw * H * Nx;   // first row of this half
+  const double *fin = A.in_f + rowh, *cin = nfc ? A.in_c + rowh : nullptr;
+
+  double yf[NG], yc[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int j = q < ng ? k0 + q : k0;
+    yf[q] = inside ? fin[(int64_t)j * Nx + i] : 0.0;
+    yc[q] = (inside && nfc) ? cin[(int64_t)j * Nx + i] : 0.0;
+  }
+  // wall ghosts (Sec. IV.C.3): incoming nodes extrapolated quadratically
+  // from the three nearest cells, emergent nodes n_w g^w_k in all three
+  const bool needL = win.i0 < kHalo, needR = win.i0 - kHalo + 63 >= Nx;
+  if ((hw == 1 && needL) || (hw == 0 && needR)) {
+    const bool lw = hw == 1;
+    const int l0 = lw ? kHalo : Nx - 1 - (win.i0 - kHalo);
+    const int dl = lw ? 1 : -1;
+    const int gi = lw ? -i : i - Nx + 1;
+    const double c0 = gi == 1 ? 3.0 : (gi == 2 ? 6.0 : 10.0);
+    const double c1 = gi == 1 ? -3.0 : (gi == 2 ? -8.0 : -15.0);
+    const double c2 = gi == 1 ? 1.0 : (gi == 2 ? 3.0 : 6.0);
+    const bool ghost = gi >= 1 && gi <= 3;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const double y0 = readlane_d(yf[q], l0), y1 = readlane_d(yf[q], l0 + dl), y2 = readlane_d(yf[q], l0 + 2 * dl);
+      const double x0 = readlane_d(yc[q], l0), x1 = readlane_d(yc[q], l0 + dl), x2 = readlane_d(yc[q], l0 + 2 * dl);
+      if (ghost) {
+        yf[q] = c0 * y0 + c1 * y1 + c2 * y2;
+        yc[q] = c0 * x0 + c1 * x1 + c2 * x2;
+      }
+    }
+  }
+  const double nL = A.lnw[2 * win.ch], nR = A.lnw[2 * win.ch + 1];
+  if (hw == 0 && i < 0) {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int k = q < ng ? k0 + q : k0;
+      yf[q] = nL * A.gw[C.gw_off + k];
+      yc[q] = nfc ? C.half_Dt * C.TL * yf[q] : 0.0;
+    }
+  }
+  if (hw == 1 && i >= Nx && i <= Nx + 2) {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int k = q < ng ? k0 + q : k0;
+      yf[q] = nR * A.gw[C.gw_off + 2 * H + H + k];
+      yc[q] = nfc ? C.half_Dt * C.TR * yf[q] : 0.0;
+    }
+  }
+
+  // force: within-half block from the transposed table, one pass over the
+  // half's rows of this lane's cell; the rank-1 cross term from the cell phase
+  double kf[NG], kc[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) kf[q] = kc[q] = 0.0;
+  for (int j = 0; j < H; ++j) {
+    const double vf = fin[(int64_t)j * Nx + ic];
+    const double vc = nfc ? cin[(int64_t)j * Nx + ic] : 0.0;
+    const double *kt = A.KinT + (int64_t)j * H + k0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      // the last group of a half may hold fewer than NG nodes: clamp the
+      // index (every read stays inside row j) and drop the extra terms
+      const double kv = q < ng ? kt[q < ng ? q : 0] : 0.0;
+      kf[q] = fma(kv, vf, kf[q]);
+      kc[q] = fma(kv, vc, kc[q]);
+    }
+  }
+  const double *cd = A.cell + (int64_t)(C.cell_off + ic) * kCellStride;
+  const double n = cd[0], T = cd[1], inv_tau = cd[2], bf = cd[3], bc = cd[4];
+  const double *G = cd + 5 + (hw ? kNmaxLarge + 1 : 0);
+  const double eqc = C.half_Dt * T;
+  double srcf[NG], srcc[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int k = q < ng ? k0 + q : k0;
+    double geq = 0.0;
+    if (inv_tau != 0.0)
+      for (int l = 0; l <= N; ++l) geq = fma(A.HWs[(int64_t)k * (N + 1) + l], G[l], geq);
+    srcf[q] = -C.g * sg * (kf[q] + tl->ka[k] * bf) - (yf[q] - n * geq) * inv_tau;
+    srcc[q] = -C.g * sg * (kc[q] + tl->ka[k] * bc) - (yc[q] - eqc * n * geq) * inv_tau;
+  }
+
+  // advection (lane-parallel face values) and the RK-3 combination
+  const FaceCoef fcoef = face_coef(hw);
+  const bool face_used = inside && lane >= kHalo - 1 + hw && lane < kHalo + kWin + hw;
+  const bool wall_face = hw == 0 ? (i == -1) : (i == Nx);
+  const bool out_lane = lane >= kHalo && lane < kHalo + kWin && inside;
+  const double dx_inv = A.inv_dx[C.cell_off + ic];
+  const double sdx = hw == 0 ? -dx_inv : dx_inv;
+  const bool need_base = A.a_base != 0.0;
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    if (q >= ng) break;
+    const int k = k0 + q;
+    const double v = A.p[hw * H + k];
+    const int64_t o = rowh + (int64_t)k * Nx + ic;
+#pragma unroll
+    for (int fn = 0; fn < 2; ++fn) {
+      if (fn == 1 && !nfc) break;
+      const double y0v = fn == 0 ? yf[q] : yc[q];
+      double fv = face_value_lanes<ADV>(y0v, fcoef, face_used);
+      if (wall_face) fv = y0v;
+      const double F = v * fv;
+      const double Fo = hw == 0 ? dpp_shr1(F) : dpp_shl1(F);
+      const double L = fma(sdx, F - Fo, fn == 0 ? srcf[q] : srcc[q]);
+      const double base = need_base ? (fn == 0 ? A.base_f : A.base_c)[o] : 0.0;
+      const double yn = A.a_base * base + A.b_stage * (y0v + C.dt * L);
+      if (out_lane) (fn == 0 ? A.out_f : A.out_c)[o] = yn;
+    }
+  }
+}
+
+}  // namespace hhlb

@@ -21,4 +21,9 @@ void register_mixed_f32(LaunchMap &m);
 void register_mixed_bf16(LaunchMap &m);
 void register_mixed_f16(LaunchMap &m);
 
+// The node-parallel FP64 stage of large half-range classes (Q > 16):
+// kernels_large.hip.
+struct LargeArgs;
+void launch_large(const LargeArgs &a, int adv, int H, hipStream_t s);
+
 }  // namespace hhlb

@@ -47,7 +47,7 @@ constexpr int kHalo = 3;
 
 // Per model class (quadrature, Q, N, p0): uploaded once.
 struct DevTables {
-  double p[2 * kQmaxDev];                 // p_k / m
+  double p[2 * 256];                      // p_k / m (every node, also of the large-Q classes)
   double z[kQmaxDev], w[kQmaxDev];        // positive nodes (units of p0), weights
   double a[kQmaxDev + 2];                 // recurrence: sqrt(b_{l+1}) h_{l+1} = (z-a_l) h_l - sqrt(b_l) h_{l-1}
   double sb[kQmaxDev + 3];                // sqrt(b_l)

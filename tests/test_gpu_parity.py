@@ -92,6 +92,34 @@ def test_half_range_laguerre():
     _check(chans, 40, perturb=0.03, what="half-range Laguerre")
 
 
+def test_large_q_node_parallel():
+    """Q > 16 (the node-parallel stage): HHLB(19;20) WENO-5 with chi over two
+    windows (the second ragged) on a stretched grid with a perturbed start;
+    HHLB(12;17) upwind-3 with N < Q-1; HHLB(20;40) collisionless."""
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=20, N=19, Nx=70, adv=h.WENO5, transverse_dof=2,
+                       stretch_A=0.8, Kn=0.05, g=-0.5, T_left=1.0, T_right=1.6, dt=-0.5),
+             h.Channel(quad=h.HALF_HERMITE, Q=17, N=12, Nx=59, adv=h.UPWIND3, transverse_dof=2,
+                       Kn=0.2, g=0.3, T_left=1.2, T_right=1.0, dt=-0.5),
+             h.Channel(quad=h.HALF_HERMITE, Q=40, N=20, Nx=24, adv=h.WENO5, transverse_dof=0,
+                       stretch_A=0.9, Kn=math.inf, g=0.1, T_left=1.4, T_right=0.6, dt=-0.5)]
+    _check(chans, 20, perturb=0.03, what="large Q")
+
+
+def test_ballistic_hhlb_20_200_setup():
+    """The paper's ballistic configuration (Sec. VI.D): HHLB(20;200), V = 400,
+    Nx = 24, A = 0.99, Kn = inf, g = 0.1, T_left = 1.4, T_right = 0.6,
+    dt = 1e-4, the 1-D gas (no chi); 40 steps against the oracle from the
+    equilibrium at rest.  The start is smooth in p on purpose: at V = 400 the
+    force matrix differentiates like a 400-point spectral operator, so a
+    start perturbed at random node by node gives force terms 1e6 times the
+    populations and compares rounding orders rather than the method."""
+    h = H()
+    ch = h.Channel(quad=h.HALF_HERMITE, Q=200, N=20, Nx=24, adv=h.WENO5, transverse_dof=0,
+                   stretch_A=0.99, Kn=math.inf, g=0.1, T_left=1.4, T_right=0.6, dt=1e-4)
+    _check([ch], 40, what="HHLB(20;200)")
+
+
 def test_edge_cases_batch():
     """Minimum Nx = 8 (both walls in one window), collisionless Kn = inf,
     no chi (Dt = 0), N < Q - 1, p0 != 1, positive g, a mixed batch of model

@@ -95,8 +95,15 @@ def test_create_rejects_bad_arguments(bad):
 
 
 def test_create_unsupported_shape_and_null_calls():
-    st, _ = _create([H.Channel(Q=20)])
+    # Q > 16 runs the node-parallel stage: FP64, half-range Hermite, N <= 20
+    st, _ = _create([H.Channel(Q=24, N=21)])
     assert st == -2
+    st, _ = _create([H.Channel(quad=H.FULL_HERMITE, Q=20)])
+    assert st == -2
+    st, _ = _create([H.Channel(Q=24)], precision=H.MIXED_F32)
+    assert st == -2
+    st, h = _create([H.Channel(Q=24)])
+    assert st == 0 and H.lib().hhlb_destroy(h) == 0
     L = H.lib()
     assert L.hhlb_step(None, 1) == -1
     assert L.hhlb_workspace_bytes(None, None) == -1
