@@ -3,13 +3,14 @@
 // HHLB(20;Q) models of the ballistic study (Sec. VI.D).  A lane holds one
 // cell, as in stage_kernel_half, but the Q nodes of a half no longer fit a
 // lane's registers, so one stage runs as two kernels:
-//   large_cell_kernel: per cell, the moments (Eq. fmoms), 1/tau, the rank-1
-//     force projections and the half-range equilibrium coefficients of both
-//     halves (Sec. IV.B.3, the change of variables of stage_kernel_half);
-//     per channel, the wall densities (Eq. nplus_def).
-//   large_node_kernel: per window and group of NG nodes of one half, the
-//     wall ghosts (Sec. IV.C.3), the force -F (K y)_k with the within-half
-//     block read from a transposed table (Eq. hh_Kk_hh), BGK towards the
+//   large_cell_kernel: one wave per cell, lanes over nodes and then over
+//     quadrature points: the moments (Eq. fmoms), 1/tau, the rank-1 force
+//     projections and the half-range equilibrium coefficients of both halves
+//     (Sec. IV.B.3, the change of variables of stage_kernel_half); per
+//     channel, the wall densities (Eq. nplus_def).
+//   large_node_kernel: per window and tile of 16 nodes of one half, the
+//     force -F (K y)_k with the within-half block (Eq. hh_Kk_hh) contracted
+//     on FP64 MFMA tiles, the wall ghosts (Sec. IV.C.3), BGK towards the
 //     synthesised equilibrium, WENO-5 / upwind-3 advection (the lane-parallel
 //     face values of stage_kernel_half) and the RK-3 combination.
 #pragma once
@@ -20,7 +21,6 @@ namespace hhlb {
 constexpr int kQmaxLarge = 256;   // nodes per half
 constexpr int kNmaxLarge = 20;    // equilibrium order
 constexpr int kCellStride = 48;   // doubles per cell in the cell-phase output
-constexpr int kLargeNG = 8;       // nodes per block of the node phase
 
 // Tables of one large model class.  The transposed within-half block
 // KinT[j * H + k] = Kin[k][j] and HWs[k * (N+1) + l] follow the struct.
@@ -52,74 +52,96 @@ struct LargeArgs {
   int32_t nfun;
 };
 
-// Cell phase.  Wave 0: lane = cell of the window (lanes 0..kWin-1).  Wave 1:
-// the left-wall density if the window holds cell 0; wave 2: the right-wall
-// density if it holds cell Nx-1 (lanes over the incoming nodes).
+// Cell phase: blockIdx.x = window.  For blockIdx.y < kCellGroups each wave
+// takes one cell, i0 + 4 blockIdx.y + wave: its lanes run over the V nodes
+// for the moments and projections, then over the quadrature points of the
+// equilibrium (the main rule and the correction), and wave sums collect
+// both.  Block kCellGroups: wave 0 the left-wall density if the window holds
+// cell 0, wave 1 the right-wall one if it holds cell Nx-1 (lanes over the
+// incoming nodes).
+constexpr int kCellGroups = (kWin + 3) / 4;
+
 template <int ADV>
-__global__ __launch_bounds__(192) void large_cell_kernel(LargeArgs A) {
+__global__ __launch_bounds__(256) void large_cell_kernel(LargeArgs A) {
   const DevWindow win = A.wins[blockIdx.x];
   const DevChannel C = A.chans[win.ch];
   const DevLarge *tl = A.tl;
   const int H = tl->H, V = 2 * H, N = tl->N, Nx = C.Nx;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const double *yf = A.in_f + C.off, *yc = A.nfun > 1 ? A.in_c + C.off : nullptr;
-  if (wave == 0) {
-    const int i = win.i0 + lane;
-    const bool act = lane < kWin && i < Nx;
-    const int ic = act ? i : Nx - 1;
+  if (blockIdx.y < kCellGroups) {
+    const int r = 4 * (int)blockIdx.y + wave;
+    const int i = win.i0 + r;
+    if (r >= kWin || i >= Nx) return;   // wave-uniform
     double n = 0, mom = 0, s2 = 0, ech = 0, bf = 0, bc = 0;
-    for (int k = 0; k < V; ++k) {
-      const double v = A.p[k], y = yf[(int64_t)k * Nx + ic], kbv = tl->kb[k < H ? k : k - H];
+    for (int k = lane; k < V; k += 64) {
+      const double v = A.p[k], y = yf[(int64_t)k * Nx + i], kbv = tl->kb[k < H ? k : k - H];
       n += y;
       mom += v * y;
       s2 += v * v * y;
       bf += kbv * y;
       if (yc) {
-        const double x = yc[(int64_t)k * Nx + ic];
+        const double x = yc[(int64_t)k * Nx + i];
         ech += x;
         bc += kbv * x;
       }
     }
+    n = wave_sum(n);
+    mom = wave_sum(mom);
+    s2 = wave_sum(s2);
+    bf = wave_sum(bf);
+    if (yc) {
+      ech = wave_sum(ech);
+      bc = wave_sum(bc);
+    }
     const double u = mom / n;
     const double T = (s2 - u * mom + 2.0 * ech) * C.inv_1pDt / n;
-    double *out = A.cell + (int64_t)(C.cell_off + ic) * kCellStride;
     double Gp[kNmaxLarge + 1], Gm[kNmaxLarge + 1];
 #pragma unroll
     for (int l = 0; l <= kNmaxLarge; ++l) Gp[l] = Gm[l] = 0.0;
     if (C.inv_Kn != 0.0) {
       const double sT = sqrt(T), s = sT * tl->inv_p0, y0 = -u / sT;
-      auto accum = [&](double *G, double x, double wt) {
+      auto accum = [&](double (&G)[kNmaxLarge + 1], double x, double wt) {
         double qm = 1.0, q = x - tl->a[0];
         G[0] += wt;
         if (N >= 1) G[1] += wt * q;
 #pragma unroll
         for (int l = 1; l < kNmaxLarge; ++l) {
-          if (l + 1 > N) break;
-          const double qn = (x - tl->a[l]) * q - tl->mb[l] * qm;
-          qm = q;
-          q = qn;
-          G[l + 1] += wt * q;
+          if (l + 1 <= N) {
+            const double qn = (x - tl->a[l]) * q - tl->mb[l] * qm;
+            qm = q;
+            q = qn;
+            G[l + 1] += wt * q;
+          }
         }
       };
-      for (int j = 0; j < tl->nm; ++j) {
-        accum(Gp, u * tl->inv_p0 + s * tl->zm[j], tl->wm[j]);
-        accum(Gm, -u * tl->inv_p0 + s * tl->zm[j], tl->wm[j]);
+      if (lane < tl->nm) {
+        accum(Gp, u * tl->inv_p0 + s * tl->zm[lane], tl->wm[lane]);
+        accum(Gm, -u * tl->inv_p0 + s * tl->zm[lane], tl->wm[lane]);
       }
-      const double ymax = wave_max(act ? fabs(y0) : 0.0);
+      const double ymax = fabs(y0);
       if (ymax > 0.0) {
         int li = kLadder - 1;
         for (int j = 1; j < kLadder; ++j)
           if (tl->lad_y[j] >= ymax) { li = j; break; }
         const int nc = tl->lad_n[li], o = tl->lad_off[li];
-        for (int j = 0; j < nc; ++j) {
-          const double t = tl->ltau[o + j], yt = y0 * t;
-          const double e = y0 * tl->llamw[o + j] * exp(-0.5 * yt * yt);
+        if (lane < nc) {   // nc <= kLadderPts = 64
+          const double t = tl->ltau[o + lane], yt = y0 * t;
+          const double e = y0 * tl->llamw[o + lane] * exp(-0.5 * yt * yt);
           accum(Gp, u * tl->inv_p0 * (1.0 - t), -e);
           accum(Gm, -u * tl->inv_p0 * (1.0 - t), e);
         }
       }
+#pragma unroll
+      for (int l = 0; l <= kNmaxLarge; ++l) {
+        if (l <= N) {
+          Gp[l] = wave_sum(Gp[l]);
+          Gm[l] = wave_sum(Gm[l]);
+        }
+      }
     }
-    if (act) {
+    if (lane == 0) {
+      double *out = A.cell + (int64_t)(C.cell_off + i) * kCellStride;
       out[0] = n;
       out[1] = T;
       out[2] = n * C.inv_Kn;
@@ -127,16 +149,18 @@ __global__ __launch_bounds__(192) void large_cell_kernel(LargeArgs A) {
       out[4] = bc;
 #pragma unroll
       for (int l = 0; l <= kNmaxLarge; ++l) {
-        if (l > N) break;
-        out[5 + l] = Gp[l];
-        out[5 + kNmaxLarge + 1 + l] = Gm[l];
+        if (l <= N) {
+          out[5 + l] = Gp[l];
+          out[5 + kNmaxLarge + 1 + l] = Gm[l];
+        }
       }
     }
     return;
   }
   // wall densities from the incoming wall-face fluxes of f (Eq. nplus_def):
   // ghosts extrapolated quadratically from the three nearest cells
-  const bool left = wave == 1;
+  if (wave > 1) return;
+  const bool left = wave == 0;
   if (left ? win.i0 != 0 : !(win.i0 <= Nx - 1 && Nx - 1 < win.i0 + kWin)) return;
   double acc = 0.0;
   for (int j = lane; j < H; j += 64) {
@@ -154,27 +178,111 @@ __global__ __launch_bounds__(192) void large_cell_kernel(LargeArgs A) {
   }
 }
 
-// Node phase: blockIdx.x = window, blockIdx.y = group of up to NG nodes of one
-// half (groups never straddle the halves).  One wave; lane = cell
-// i0 - kHalo + lane, as in stage_kernel_half.
-template <int ADV, int NG>
-__global__ __launch_bounds__(64) void large_node_kernel(LargeArgs A) {
+// Node phase: blockIdx.x = window, blockIdx.y = tile of 16 nodes of one half
+// (tiles never straddle the halves), four waves.  The within-half force
+// block is a contraction over the half's H rows, D[node][cell] =
+// sum_j Kin[node][j] y_j[cell], run on FP64 MFMA 16x16x4 tiles: the rows are
+// split over the four waves in steps of 4, the A operand (the transposed
+// table) and the B operand (the rows of f or chi for the window's 64 cells)
+// load straight from memory in the MFMA layout, and the four partial tiles
+// are summed through LDS.  After that wave w owns nodes kt0 + 4w .. kt0 + 4w
+// + 3, lane = cell i0 - kHalo + lane as in stage_kernel_half.
+constexpr int kNodeWaves = 4;
+constexpr int kTileNodes = 16;
+constexpr int kStepsPerWave = (kQmaxLarge / 4 + kNodeWaves - 1) / kNodeWaves;
+
+template <int ADV>
+__global__ __launch_bounds__(64 * kNodeWaves) void large_node_kernel(LargeArgs A) {
+  constexpr int NG = kTileNodes / kNodeWaves;   // nodes per wave after the reduction
+  constexpr int S = 65;                         // padded LDS row: 64 cells
+  __shared__ double s_red[kNodeWaves * kTileNodes * S];
   const DevWindow win = A.wins[blockIdx.x];
   const DevChannel C = A.chans[win.ch];
   const DevLarge *tl = A.tl;
   const int H = tl->H, N = tl->N, Nx = C.Nx;
-  const int gph = (H + NG - 1) / NG;
-  const int hw = blockIdx.y / gph;                 // 0: p > 0, 1: p < 0
-  const int k0 = (blockIdx.y % gph) * NG;          // first node within the half
-  const int ng = H - k0 < NG ? H - k0 : NG;
-  const int lane = threadIdx.x;
+  const int gph = (H + kTileNodes - 1) / kTileNodes;
+  const int hw = blockIdx.y / gph;                       // 0: p > 0, 1: p < 0
+  const int kt0 = (blockIdx.y % gph) * kTileNodes;       // first node of the tile
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = win.i0 - kHalo + lane;
   const bool inside = i >= 0 && i < Nx;
-  const int ic = inside ? i : (i < 0 ? 0 : Nx - 1);   // clamped: loads stay in bounds
+  const int ic = inside ? i : (i < 0 ? 0 : Nx - 1);      // clamped: loads stay in bounds
   const bool nfc = A.nfun > 1;
   const double sg = hw ? -1.0 : 1.0;
-  const int64_t rowh = C.off + (int64_t)hw * H * Nx;   // first row of this half
+  const int64_t rowh = C.off + (int64_t)hw * H * Nx;     // first row of this half
   const double *fin = A.in_f + rowh, *cin = nfc ? A.in_c + rowh : nullptr;
+
+  // force: MFMA contraction over this wave's share of the rows
+  const int nsteps = (H + 3) / 4, spw = (nsteps + kNodeWaves - 1) / kNodeWaves;
+  const int s0 = wave * spw;
+  const int nsw = nsteps - s0 < 0 ? 0 : (nsteps - s0 < spw ? nsteps - s0 : spw);
+  const int kr = lane >> 4, jl = lane & 15;
+  const int an = kt0 + jl;                               // A row: node
+  int bcell[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int il = win.i0 - kHalo + 16 * c + jl;
+    bcell[c] = il < 0 ? 0 : (il >= Nx ? Nx - 1 : il);
+  }
+  double av[kStepsPerWave];
+#pragma unroll
+  for (int t = 0; t < kStepsPerWave; ++t) {
+    const int row = 4 * (s0 + t) + kr;
+    const bool ok = t < nsw && row < H && an < H;
+    av[t] = A.KinT[ok ? (int64_t)row * H + an : 0];
+    if (!ok) av[t] = 0.0;
+  }
+  auto contract = [&](const double *src, dbl4 acc[4]) {
+    double bv[kStepsPerWave][4];
+#pragma unroll
+    for (int t = 0; t < kStepsPerWave; ++t) {
+      const int row = 4 * (s0 + t) + kr;
+      const bool ok = t < nsw && row < H;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[t][c] = ok ? src[(int64_t)row * Nx + bcell[c]] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < kStepsPerWave; ++t) {
+      if (t >= nsw) break;   // wave-uniform: MFMA runs with every lane active
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t][c], acc[c], 0, 0, 0);
+    }
+  };
+  // D[node 4r + kr][cell 16c + jl] sits in acc[c][r]; partial tiles to LDS,
+  // then wave w sums its NG nodes over the four partials
+  auto reduce = [&](const dbl4 acc[4], double out[NG]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s_red[(wave * kTileNodes + 4 * r + kr) * S + 16 * c + jl] = acc[c][r];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < kNodeWaves; ++w) v += s_red[(w * kTileNodes + wave * NG + q) * S + lane];
+      out[q] = v;
+    }
+    __syncthreads();
+  };
+  double kf[NG], kc[NG];
+  {
+    dbl4 accf[4];
+    contract(fin, accf);
+    reduce(accf, kf);
+  }
+#pragma unroll
+  for (int q = 0; q < NG; ++q) kc[q] = 0.0;
+  if (nfc) {   // uniform over the block
+    dbl4 accc[4];
+    contract(cin, accc);
+    reduce(accc, kc);
+  }
+  const int k0 = kt0 + wave * NG;                        // first node of this wave
+  const int ng = H - k0 < NG ? H - k0 : NG;              // may be <= 0 in the last tile
+  if (ng <= 0) return;   // wave-uniform, after the last barrier
 
   double yf[NG], yc[NG];
 #pragma unroll
@@ -223,24 +331,6 @@ __global__ __launch_bounds__(64) void large_node_kernel(LargeArgs A) {
     }
   }
 
-  // force: within-half block from the transposed table, one pass over the
-  // half's rows of this lane's cell; the rank-1 cross term from the cell phase
-  double kf[NG], kc[NG];
-#pragma unroll
-  for (int q = 0; q < NG; ++q) kf[q] = kc[q] = 0.0;
-  for (int j = 0; j < H; ++j) {
-    const double vf = fin[(int64_t)j * Nx + ic];
-    const double vc = nfc ? cin[(int64_t)j * Nx + ic] : 0.0;
-    const double *kt = A.KinT + (int64_t)j * H + k0;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      // the last group of a half may hold fewer than NG nodes: clamp the
-      // index (every read stays inside row j) and drop the extra terms
-      const double kv = q < ng ? kt[q < ng ? q : 0] : 0.0;
-      kf[q] = fma(kv, vf, kf[q]);
-      kc[q] = fma(kv, vc, kc[q]);
-    }
-  }
   const double *cd = A.cell + (int64_t)(C.cell_off + ic) * kCellStride;
   const double n = cd[0], T = cd[1], inv_tau = cd[2], bf = cd[3], bc = cd[4];
   const double *G = cd + 5 + (hw ? kNmaxLarge + 1 : 0);
