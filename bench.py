@@ -363,6 +363,36 @@ def run_form(H, torch, np, chans, form, args):
     return rec, mom
 
 
+def run_ballistic(H, torch, np, steps=2000, warmup=32):
+    """The node-parallel path on the paper's ballistic set-up (Sec. VI.D):
+    HHLB(20;200), V = 400, Nx = 24, A = 0.99, dt = 1e-4, Kn = inf, no chi,
+    its eight cases (g_p in {0.1, 1} x Delta T in {0.6, 0.3, 0, -0.4}) as one
+    batch, from the equilibrium at rest.  HIP events on the solver's stream."""
+    cases = [(gp, dT) for gp in (0.1, 1.0) for dT in (0.6, 0.3, 0.0, -0.4)]
+    chans = [H.Channel(quad=H.HALF_HERMITE, Q=200, N=20, Nx=24, adv=H.WENO5, transverse_dof=0,
+                       stretch_A=0.99, Kn=math.inf, g=-gp, T_left=1 - dT, T_right=1 + dT, dt=1e-4)
+             for gp, dT in cases]
+    s = H.Solver(chans)
+    s.init_equilibrium()
+    s.step(warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    _, _, bad = s.diagnostics()
+    assert int(bad.item()) == 0, "ballistic: non-finite populations"
+    nu = sum(c.V * c.Nx for c in chans)
+    s.close()
+    return {"workload": "HHLB(20;200) V=400, 8 channels (the paper's ballistic cases) x Nx=24 "
+                        "tanh-stretched (A=0.99), WENO5+RK3, Kn=inf, dt=1e-4, f only, FP64, "
+                        "node-parallel stage (cell kernel + MFMA node kernel per RK stage)",
+            "value": nu * steps / (ms / 1e3), "unit": "node-updates/s",
+            "ms_per_step": ms / steps, "steps": steps}
+
+
 def moment_diff(np, a, b):
     """err_n = max|dn|/max n, err_u = max|du|/sqrt(T_left), err_T = max|dT|/max T."""
     n0, u0, T0 = a
@@ -392,6 +422,8 @@ def main():
     ap.add_argument("--residual", type=float, default=1e-10)
     ap.add_argument("--check-every", type=int, default=1000)
     ap.add_argument("--max-steps", type=int, default=3_000_000)
+    ap.add_argument("--no-ballistic", action="store_true",
+                    help="skip the HHLB(20;200) ballistic record (the node-parallel path)")
     ap.add_argument("--no-laguerre", action="store_true",
                     help="skip the FP64 timing of the half-range Gauss-Laguerre velocity set")
     ap.add_argument("--cpu-channels", type=int, default=8)
@@ -478,6 +510,9 @@ def main():
                         f"(Q=16, V=32, p0={LAGUERRE_P0}), FP64",
             "value": r["value"], "unit": "node-updates/s", "ms_per_step": r["ms_per_step"],
             "mass_drift": r["mass_drift"], "avg_launch_us": r["roofline"]["avg_launch_us"]}
+    if not args.no_ballistic:
+        print("[bench] ballistic HHLB(20;200): 8 channels x Nx=24", file=sys.stderr, flush=True)
+        out["ballistic_q200"] = run_ballistic(H, torch, np)
     if args.batch_channels > 0:
         out["batched"] = run_batch(H, torch, np, args)
     if not args.no_cpu_baseline:

@@ -985,6 +985,7 @@ void enqueue_class_stage(hhlb_solver *s, size_t ci, int stage, const void *inf, 
     la.lnw = (double *)(s->ws + s->o_lnw);
     la.nwall = (double *)(s->ws + s->o_nwall);
     la.nfun = mc.Dt > 0 ? 2 : 1;
+    la.xcd_map = s->tuning.xcd_map;
     hhlb::launch_large(la, mc.adv, mc.rule.H, stream);
     return;
   }

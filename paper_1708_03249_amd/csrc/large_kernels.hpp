@@ -50,41 +50,57 @@ struct LargeArgs {
   double *lnw;                    // wall densities of this stage, 2 per channel
   double *nwall;                  // diagnostics copy (written in stage 2)
   int32_t nfun;
+  int32_t xcd_map;                // 1: the blocks of a window run on one XCD
 };
 
-// Cell phase: blockIdx.x = window.  For blockIdx.y < kCellGroups each wave
-// takes one cell, i0 + 4 blockIdx.y + wave: its lanes run over the V nodes
-// for the moments and projections, then over the quadrature points of the
-// equilibrium (the main rule and the correction), and wave sums collect
-// both.  Block kCellGroups: wave 0 the left-wall density if the window holds
-// cell 0, wave 1 the right-wall one if it holds cell Nx-1 (lanes over the
-// incoming nodes).
+// Cell phase: a 1-D grid of nwin x (kCellGroups + 1) blocks; block b maps to
+// window w and group y (with xcd_map, the groups of a window run on one
+// XCD, so the cache lines its cells share stay in one L2).  For y <
+// kCellGroups each wave takes one cell, i0 + 4 y + wave: its lanes run over
+// the V nodes for the moments and projections, then over the quadrature
+// points of the equilibrium (the main rule and the correction), and wave
+// sums collect both.  Group kCellGroups: wave 0 the left-wall density if the
+// window holds cell 0, wave 1 the right-wall one if it holds cell Nx-1
+// (lanes over the incoming nodes).
 constexpr int kCellGroups = (kWin + 3) / 4;
 
 template <int ADV>
 __global__ __launch_bounds__(256) void large_cell_kernel(LargeArgs A) {
-  const DevWindow win = A.wins[blockIdx.x];
+  constexpr int G = kCellGroups + 1;
+  const int lb = A.xcd_map ? xcd_window(blockIdx.x, A.nwin * G) : (int)blockIdx.x;
+  const int gy = lb % G;
+  const DevWindow win = A.wins[lb / G];
   const DevChannel C = A.chans[win.ch];
   const DevLarge *tl = A.tl;
   const int H = tl->H, V = 2 * H, N = tl->N, Nx = C.Nx;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const double *yf = A.in_f + C.off, *yc = A.nfun > 1 ? A.in_c + C.off : nullptr;
-  if (blockIdx.y < kCellGroups) {
-    const int r = 4 * (int)blockIdx.y + wave;
+  if (gy < kCellGroups) {
+    const int r = 4 * gy + wave;
     const int i = win.i0 + r;
     if (r >= kWin || i >= Nx) return;   // wave-uniform
+    // V <= 2 kQmaxLarge = 8 x 64: a fixed trip count and unconditional loads
+    // (clamped index, the surplus terms selected away), so they issue at once
+    constexpr int KT = 2 * kQmaxLarge / 64;
+    double yv[KT], xv[KT];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      const int k = lane + 64 * t, kk = k < V ? k : V - 1;
+      yv[t] = yf[(int64_t)kk * Nx + i];
+      xv[t] = yc ? yc[(int64_t)kk * Nx + i] : 0.0;
+    }
     double n = 0, mom = 0, s2 = 0, ech = 0, bf = 0, bc = 0;
-    for (int k = lane; k < V; k += 64) {
-      const double v = A.p[k], y = yf[(int64_t)k * Nx + i], kbv = tl->kb[k < H ? k : k - H];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      const int k = lane + 64 * t, kk = k < V ? k : V - 1;
+      const double v = A.p[kk], kbv = tl->kb[kk < H ? kk : kk - H];
+      const double y = k < V ? yv[t] : 0.0, x = k < V ? xv[t] : 0.0;
       n += y;
       mom += v * y;
       s2 += v * v * y;
       bf += kbv * y;
-      if (yc) {
-        const double x = yc[(int64_t)k * Nx + i];
-        ech += x;
-        bc += kbv * x;
-      }
+      ech += x;
+      bc += kbv * x;
     }
     n = wave_sum(n);
     mom = wave_sum(mom);
@@ -178,8 +194,10 @@ __global__ __launch_bounds__(256) void large_cell_kernel(LargeArgs A) {
   }
 }
 
-// Node phase: blockIdx.x = window, blockIdx.y = tile of 16 nodes of one half
-// (tiles never straddle the halves), four waves.  The within-half force
+// Node phase: a 1-D grid of nwin x 2 ceil(H/16) blocks; block b maps to a
+// window and a tile of 16 nodes of one half (tiles never straddle the
+// halves), four waves.  With xcd_map the tiles of a window run on one XCD:
+// they all read the window's rows, which then stay in that XCD's L2.  The within-half force
 // block is a contraction over the half's H rows, D[node][cell] =
 // sum_j Kin[node][j] y_j[cell], run on FP64 MFMA 16x16x4 tiles: the rows are
 // split over the four waves in steps of 4, the A operand (the transposed
@@ -187,22 +205,32 @@ __global__ __launch_bounds__(256) void large_cell_kernel(LargeArgs A) {
 // load straight from memory in the MFMA layout, and the four partial tiles
 // are summed through LDS.  After that wave w owns nodes kt0 + 4w .. kt0 + 4w
 // + 3, lane = cell i0 - kHalo + lane as in stage_kernel_half.
-constexpr int kNodeWaves = 4;
+#ifndef HHLB_LARGE_WAVES
+#define HHLB_LARGE_WAVES 4   // waves per node-phase block (the rows split over them)
+#endif
+#ifndef HHLB_LARGE_OCC
+#define HHLB_LARGE_OCC 2     // waves per SIMD the node phase is compiled for
+#endif
+constexpr int kNodeWaves = HHLB_LARGE_WAVES;
 constexpr int kTileNodes = 16;
 constexpr int kStepsPerWave = (kQmaxLarge / 4 + kNodeWaves - 1) / kNodeWaves;
 
 template <int ADV>
-__global__ __launch_bounds__(64 * kNodeWaves) void large_node_kernel(LargeArgs A) {
+__global__ __launch_bounds__(64 * kNodeWaves) __attribute__((amdgpu_waves_per_eu(HHLB_LARGE_OCC))) void large_node_kernel(LargeArgs A) {
   constexpr int NG = kTileNodes / kNodeWaves;   // nodes per wave after the reduction
   constexpr int S = 65;                         // padded LDS row: 64 cells
   __shared__ double s_red[kNodeWaves * kTileNodes * S];
-  const DevWindow win = A.wins[blockIdx.x];
-  const DevChannel C = A.chans[win.ch];
+  __shared__ double s_hw[kTileNodes * (kNmaxLarge + 1)];   // HWs rows of the tile
   const DevLarge *tl = A.tl;
-  const int H = tl->H, N = tl->N, Nx = C.Nx;
-  const int gph = (H + kTileNodes - 1) / kTileNodes;
-  const int hw = blockIdx.y / gph;                       // 0: p > 0, 1: p < 0
-  const int kt0 = (blockIdx.y % gph) * kTileNodes;       // first node of the tile
+  const int H = tl->H, N = tl->N;
+  const int gph = (H + kTileNodes - 1) / kTileNodes, ntile = 2 * gph;
+  const int lb = A.xcd_map ? xcd_window(blockIdx.x, A.nwin * ntile) : (int)blockIdx.x;
+  const int ty = lb % ntile;
+  const DevWindow win = A.wins[lb / ntile];
+  const DevChannel C = A.chans[win.ch];
+  const int Nx = C.Nx;
+  const int hw = ty / gph;                               // 0: p > 0, 1: p < 0
+  const int kt0 = (ty % gph) * kTileNodes;               // first node of the tile
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = win.i0 - kHalo + lane;
   const bool inside = i >= 0 && i < Nx;
@@ -211,6 +239,12 @@ __global__ __launch_bounds__(64 * kNodeWaves) void large_node_kernel(LargeArgs A
   const double sg = hw ? -1.0 : 1.0;
   const int64_t rowh = C.off + (int64_t)hw * H * Nx;     // first row of this half
   const double *fin = A.in_f + rowh, *cin = nfc ? A.in_c + rowh : nullptr;
+
+  // the tile's equilibrium rows HWs[k][0..N] (read after the first barrier)
+  for (int t = threadIdx.x; t < kTileNodes * (kNmaxLarge + 1); t += 64 * kNodeWaves) {
+    const int q = t / (kNmaxLarge + 1), l = t % (kNmaxLarge + 1), k = kt0 + q;
+    s_hw[t] = (k < H && l <= N) ? A.HWs[(int64_t)k * (N + 1) + l] : 0.0;
+  }
 
   // force: MFMA contraction over this wave's share of the rows
   const int nsteps = (H + 3) / 4, spw = (nsteps + kNodeWaves - 1) / kNodeWaves;
@@ -333,15 +367,21 @@ __global__ __launch_bounds__(64 * kNodeWaves) void large_node_kernel(LargeArgs A
 
   const double *cd = A.cell + (int64_t)(C.cell_off + ic) * kCellStride;
   const double n = cd[0], T = cd[1], inv_tau = cd[2], bf = cd[3], bc = cd[4];
-  const double *G = cd + 5 + (hw ? kNmaxLarge + 1 : 0);
+  const double *Gp = cd + 5 + (hw ? kNmaxLarge + 1 : 0);
+  double G[kNmaxLarge + 1];   // fixed trip count: the loads issue together
+#pragma unroll
+  for (int l = 0; l <= kNmaxLarge; ++l) G[l] = l <= N ? Gp[l] : 0.0;
   const double eqc = C.half_Dt * T;
   double srcf[NG], srcc[NG];
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
     const int k = q < ng ? k0 + q : k0;
+    const double *hwr = s_hw + (wave * NG + (q < ng ? q : 0)) * (kNmaxLarge + 1);
     double geq = 0.0;
-    if (inv_tau != 0.0)
-      for (int l = 0; l <= N; ++l) geq = fma(A.HWs[(int64_t)k * (N + 1) + l], G[l], geq);
+    if (inv_tau != 0.0) {
+#pragma unroll
+      for (int l = 0; l <= kNmaxLarge; ++l) geq = fma(hwr[l], G[l], geq);
+    }
     srcf[q] = -C.g * sg * (kf[q] + tl->ka[k] * bf) - (yf[q] - n * geq) * inv_tau;
     srcc[q] = -C.g * sg * (kc[q] + tl->ka[k] * bc) - (yc[q] - eqc * n * geq) * inv_tau;
   }

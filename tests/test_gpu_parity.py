@@ -106,6 +106,38 @@ def test_large_q_node_parallel():
     _check(chans, 20, perturb=0.03, what="large Q")
 
 
+def test_large_q_launch_configurations_identical():
+    """The node-parallel path gives the same bits with and without the
+    XCD-aware block mapping, with direct launches and with graph replay of
+    several lengths (each block computes the same values whatever its
+    position in the grid)."""
+    import torch
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=24, N=20, Nx=150, adv=h.WENO5, transverse_dof=2,
+                       stretch_A=0.7, Kn=0.1, g=-0.3, T_left=1.0, T_right=1.3, dt=-0.5),
+             h.Channel(quad=h.HALF_HERMITE, Q=40, N=20, Nx=70, adv=h.UPWIND3, transverse_dof=0,
+                       Kn=math.inf, g=0.2, T_left=1.2, T_right=0.9, dt=-0.5)]
+    states = initial_states(chans, seed=3)
+    f0 = torch.from_numpy(np.concatenate([st[0].ravel() for st in states])).cuda()
+    c0 = torch.from_numpy(np.concatenate([st[1].ravel() for st in states])).cuda()
+    configs = [dict(), dict(xcd_map=0), dict(graph_steps=16, xcd_map=1), dict(graph_steps=3, xcd_map=0)]
+    outs = []
+    for cfg in configs:
+        s = h.Solver(chans)
+        s.set_tuning(**cfg)
+        s.set_state(f0, c0)
+        s.step(5)
+        s.step(6)
+        f, c = s.get_state()
+        torch.cuda.synchronize()
+        outs.append((f.cpu().numpy(), c.cpu().numpy()))
+        s.close()
+    assert np.all(np.isfinite(outs[0][0]))
+    for k in range(1, len(outs)):
+        assert np.array_equal(outs[0][0], outs[k][0]), configs[k]
+        assert np.array_equal(outs[0][1], outs[k][1]), configs[k]
+
+
 def test_ballistic_hhlb_20_200_setup():
     """The paper's ballistic configuration (Sec. VI.D): HHLB(20;200), V = 400,
     Nx = 24, A = 0.99, Kn = inf, g = 0.1, T_left = 1.4, T_right = 0.6,
