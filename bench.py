@@ -363,14 +363,18 @@ def run_form(H, torch, np, chans, form, args):
     return rec, mom
 
 
-def run_ballistic(H, torch, np, steps=2000, warmup=32):
+def run_ballistic(H, torch, np, nx=24, steps=2000, warmup=32):
     """The node-parallel path on the paper's ballistic set-up (Sec. VI.D):
-    HHLB(20;200), V = 400, Nx = 24, A = 0.99, dt = 1e-4, Kn = inf, no chi,
-    its eight cases (g_p in {0.1, 1} x Delta T in {0.6, 0.3, 0, -0.4}) as one
-    batch, from the equilibrium at rest.  HIP events on the solver's stream."""
+    HHLB(20;200), V = 400, Nx = 24 (or nx), A = 0.99, dt = 1e-4, Kn = inf, no
+    chi, its eight cases (g_p in {0.1, 1} x Delta T in {0.6, 0.3, 0, -0.4})
+    as one batch, from the equilibrium at rest.  The paper's dt = 1e-4 is
+    stable at Nx = 24 only (the stretched grid's smallest cell shrinks with
+    Nx); other nx take the CFL 0.5 step.  HIP events on the solver's
+    stream."""
+    dt = 1e-4 if nx == 24 else -0.5
     cases = [(gp, dT) for gp in (0.1, 1.0) for dT in (0.6, 0.3, 0.0, -0.4)]
-    chans = [H.Channel(quad=H.HALF_HERMITE, Q=200, N=20, Nx=24, adv=H.WENO5, transverse_dof=0,
-                       stretch_A=0.99, Kn=math.inf, g=-gp, T_left=1 - dT, T_right=1 + dT, dt=1e-4)
+    chans = [H.Channel(quad=H.HALF_HERMITE, Q=200, N=20, Nx=nx, adv=H.WENO5, transverse_dof=0,
+                       stretch_A=0.99, Kn=math.inf, g=-gp, T_left=1 - dT, T_right=1 + dT, dt=dt)
              for gp, dT in cases]
     s = H.Solver(chans)
     s.init_equilibrium()
@@ -386,8 +390,9 @@ def run_ballistic(H, torch, np, steps=2000, warmup=32):
     assert int(bad.item()) == 0, "ballistic: non-finite populations"
     nu = sum(c.V * c.Nx for c in chans)
     s.close()
-    return {"workload": "HHLB(20;200) V=400, 8 channels (the paper's ballistic cases) x Nx=24 "
-                        "tanh-stretched (A=0.99), WENO5+RK3, Kn=inf, dt=1e-4, f only, FP64, "
+    return {"workload": f"HHLB(20;200) V=400, 8 channels (the paper's ballistic cases) x Nx={nx} "
+                        "tanh-stretched (A=0.99), WENO5+RK3, Kn=inf, "
+                        + ("dt=1e-4" if nx == 24 else "CFL 0.5") + ", f only, FP64, "
                         "node-parallel stage (cell kernel + MFMA node kernel per RK stage)",
             "value": nu * steps / (ms / 1e3), "unit": "node-updates/s",
             "ms_per_step": ms / steps, "steps": steps}
@@ -424,6 +429,11 @@ def main():
     ap.add_argument("--max-steps", type=int, default=3_000_000)
     ap.add_argument("--no-ballistic", action="store_true",
                     help="skip the HHLB(20;200) ballistic record (the node-parallel path)")
+    ap.add_argument("--ballistic-only", action="store_true",
+                    help="only run the HHLB(20;200) ballistic record")
+    ap.add_argument("--ballistic-nx", type=int, default=24,
+                    help="cells per channel of the ballistic record")
+    ap.add_argument("--ballistic-steps", type=int, default=2000)
     ap.add_argument("--no-laguerre", action="store_true",
                     help="skip the FP64 timing of the half-range Gauss-Laguerre velocity set")
     ap.add_argument("--cpu-channels", type=int, default=8)
@@ -441,6 +451,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": n * 8, "copies": 3}))
+        return
+    if args.ballistic_only:
+        import numpy as np
+        import torch
+        import paper_1708_03249_amd as H
+        print(json.dumps({"ballistic_q200": run_ballistic(H, torch, np, nx=args.ballistic_nx,
+                                                          steps=args.ballistic_steps)}), flush=True)
         return
     if args.steady:
         import numpy as np
@@ -512,7 +529,8 @@ def main():
             "mass_drift": r["mass_drift"], "avg_launch_us": r["roofline"]["avg_launch_us"]}
     if not args.no_ballistic:
         print("[bench] ballistic HHLB(20;200): 8 channels x Nx=24", file=sys.stderr, flush=True)
-        out["ballistic_q200"] = run_ballistic(H, torch, np)
+        out["ballistic_q200"] = run_ballistic(H, torch, np, nx=args.ballistic_nx,
+                                              steps=args.ballistic_steps)
     if args.batch_channels > 0:
         out["batched"] = run_batch(H, torch, np, args)
     if not args.no_cpu_baseline:
