@@ -114,8 +114,12 @@ hhlb_status hhlb_equilibrium(int32_t quad, int32_t Q, int32_t N, double p0, doub
 /* Validate n_ch channels and build their tables on the host (extended
  * precision, rounded to double).  precision is one of the HHLB_FP64 /
  * HHLB_MIXED_* forms (a mixed form with a full-range channel is
- * HHLB_E_UNSUPPORTED).  hip_stream is a hipStream_t (NULL = default stream).
- * *out receives the solver. */
+ * HHLB_E_UNSUPPORTED).  Q <= 16 runs every kind in every form; Q > 16 runs
+ * a node-parallel FP64 stage with N <= 20 for the half-range Gauss-Hermite
+ * model up to Q = 256 and the full-range one up to Q = 512 (the HHLB(20;200)
+ * and HLB(20;500) models of Sec. VI.D); other shapes are HHLB_E_UNSUPPORTED.
+ * hip_stream is a hipStream_t (NULL = default stream).  *out receives the
+ * solver. */
 hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t precision,
                         void *hip_stream, hhlb_solver **out);
 

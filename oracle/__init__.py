@@ -92,6 +92,7 @@ def lib():
         _lib.orc_run.argtypes = [ctypes.POINTER(_Channel), ctypes.c_long, dp, dp, dp, ctypes.c_int]
         _lib.orc_moments.argtypes = [ctypes.POINTER(_Channel), dp, dp, dp, dp, dp]
         _lib.orc_set_qmono.argtypes = [ctypes.c_int]
+        _lib.orc_set_qfmono.argtypes = [ctypes.c_int]
     return _lib
 
 
@@ -118,6 +119,13 @@ def set_qmono(qmono: int) -> int:
     three-term recurrence instead of monomial coefficients (default 32).
     Returns the previous value."""
     return lib().orc_set_qmono(int(qmono))
+
+
+def set_qfmono(qfmono: int) -> int:
+    """Test-only: full-range rules with Q > qfmono are built from the
+    three-term recurrence instead of the monomial Hermite evaluation
+    (default 64).  Returns the previous value."""
+    return lib().orc_set_qfmono(int(qfmono))
 
 
 def hh_coeffs(lmax: int) -> np.ndarray:

@@ -41,6 +41,9 @@ typedef __float128 qf;
 #define ORC_QMONO 16           /* half-range Hermite: monomial construction up to
                                   this Q, the three-term recurrence beyond it   */
 #define ORC_QLAG 32            /* largest half-range Laguerre order            */
+#define ORC_QFMONO 64          /* full-range Hermite: monomial construction up to
+                                  this Q, the three-term recurrence beyond it
+                                  (up to Q = ORC_VMAX)                         */
 #define ORC_CMAX (ORC_QLAG + 2)  /* monomial rows kept: Laguerre l <= Q+1, and
                                     the recurrence rules' h_0 .. h_21          */
 
@@ -79,7 +82,7 @@ typedef struct {
   /* half-range Hermite beyond ORC_QMONO: orthonormal recurrence
    * sqrt(b_{l+1}) h_{l+1} = (z - a_l) h_l - sqrt(b_l) h_{l-1}, h_0 = 1/sqrt(b_0) */
   int rec;
-  qf ra[ORC_QMAX + 3], rb[ORC_QMAX + 4];
+  qf ra[ORC_VMAX + 3], rb[ORC_VMAX + 4];
   /* poly value at the positive nodes: P[l][k] = h_l(z_k) or He_l(z_k)       */
   qf P[ORC_QMAX + 2][ORC_QMAX];
   double p[ORC_VMAX], wd[ORC_VMAX];  /* p_k and w_k over all V nodes (double) */
@@ -535,15 +538,69 @@ static int build_full(orc_tables *t, int Q, double p0) {
   return 0;
 }
 
+/* Full-range Gauss-Hermite rule of Sec. IV.A for large Q, through the
+ * orthonormal Hermite functions h_l = He_l / sqrt(l!), which obey
+ * sqrt(l+1) h_{l+1} = z h_l - sqrt(l) h_{l-1} (a_l = 0, b_l = l, b_0 = 1):
+ *   nodes   the roots of He_Q, by Sturm bisection of that Jacobi matrix;
+ *   weights Eq. (H_wk), Q!/He_{Q+1}(z_k)^2 = 1/((Q+1) h_{Q+1}(z_k)^2);
+ *   K       Eq. (H_Kk), with He_{l+1}(z_k) He_l(z_k')/l!
+ *           = sqrt(l+1) h_{l+1}(z_k) h_l(z_k').
+ * The same formulas as build_full; the monomial evaluation there costs
+ * O(Q^4) and its roots O(Q^3) bisections, which does not reach Q = 500.
+ * P is not kept (the full-range equilibrium evaluates He_l directly). */
+static int g_qfmono = ORC_QFMONO;
+
+static int build_full_rec(orc_tables *t, int Q, double p0) {
+  if (Q % 2 || Q > ORC_VMAX) return -1;
+  const int V = Q, H = Q / 2;
+  t->quad = ORC_FULL; t->Q = Q; t->V = V; t->H = H; t->p0 = p0; t->rec = 1;
+  for (int l = 0; l <= Q + 2; ++l) t->ra[l] = 0;
+  t->rb[0] = 1;
+  for (int l = 1; l <= Q + 3; ++l) t->rb[l] = (qf)l;
+  qf *r = (qf *)malloc(sizeof(qf) * Q);
+  qf *hz = (qf *)malloc(sizeof(qf) * (size_t)V * (Q + 2));
+  qf *sq = (qf *)malloc(sizeof(qf) * (Q + 2));
+  if (!r || !hz || !sq) { free(r); free(hz); free(sq); return -1; }
+  const qf B = 4.0Q + 3.0Q * sqrtq((qf)Q);
+  sturm_roots(t, Q, -B, B, r);   /* ascending: r[H..Q-1] are the positive roots */
+  for (int k = 0; k < V; ++k) {
+    const qf z = k < H ? r[H + k] : -r[k];
+    rec_values(t, Q + 1, z, hz + (size_t)k * (Q + 2));
+  }
+  for (int k = 0; k < H; ++k) {
+    const qf hq = hz[(size_t)k * (Q + 2) + Q + 1];
+    t->z[k] = r[H + k];
+    t->w[k] = 1 / ((qf)(Q + 1) * hq * hq);
+  }
+  for (int k = 0; k < V; ++k) {
+    t->p[k] = (double)((k < H ? 1 : -1) * (qf)p0 * t->z[k % H]);
+    t->wd[k] = (double)t->w[k % H];
+  }
+  for (int l = 0; l <= Q; ++l) sq[l] = sqrtq((qf)(l + 1));
+  for (int k = 0; k < V; ++k) {
+    const qf *hk = hz + (size_t)k * (Q + 2);
+    const qf pref = -t->w[k % H] / (qf)p0;
+    for (int kp = 0; kp < V; ++kp) {
+      const qf *hp = hz + (size_t)kp * (Q + 2);
+      qf acc = 0;
+      for (int l = 0; l <= Q - 2; ++l) acc += sq[l] * hk[l + 1] * hp[l];
+      t->K[k * V + kp] = (double)(pref * acc);
+      t->Kin[k * V + kp] = t->K[k * V + kp];
+      t->Kd[k * V + kp] = 0;
+    }
+  }
+  free(r); free(hz); free(sq);
+  return 0;
+}
+
 static int build_tables(orc_tables *t, int quad, int Q, double p0) {
   memset(t, 0, sizeof(*t));
-  if (Q < 1 || Q > ORC_QMAX || !(p0 > 0)) return -1;
+  if (Q < 1 || Q > (quad == ORC_FULL ? ORC_VMAX : ORC_QMAX) || !(p0 > 0)) return -1;
   /* monomial constructions (Laguerre, and Hermite up to the switch) hold
    * c[l][s] up to l = Q + 1; the full-range roots cost O(Q^3) */
   if (quad == ORC_HALF_LAGUERRE && Q > ORC_QLAG) return -1;
-  if (quad == ORC_FULL && Q > 64) return -1;
   if (quad == ORC_HALF) return build_half(t, Q, p0);
-  if (quad == ORC_FULL) return build_full(t, Q, p0);
+  if (quad == ORC_FULL) return Q > g_qfmono ? build_full_rec(t, Q, p0) : build_full(t, Q, p0);
   if (quad == ORC_HALF_LAGUERRE) return build_half_laguerre(t, Q, p0);
   return -1;
 }
@@ -901,6 +958,14 @@ int orc_hh_coeffs(int lmax, double *out) {
 /* Test-only: half-range Hermite rules with Q above qmono (clamped to
  * 0 .. ORC_QMONO) are built from the recurrence; returns the previous value.
  * Lets the tests compare both constructions where both apply. */
+/* Test hook: full-range rules with Q > qfmono come from the recurrence
+ * construction (0 .. ORC_QFMONO); returns the previous value. */
+int orc_set_qfmono(int qfmono) {
+  int old = g_qfmono;
+  g_qfmono = qfmono < 0 ? 0 : (qfmono > ORC_QFMONO ? ORC_QFMONO : qfmono);
+  return old;
+}
+
 int orc_set_qmono(int qmono) {
   int old = g_qmono;
   g_qmono = qmono < 0 ? 0 : (qmono > ORC_QMONO ? ORC_QMONO : qmono);

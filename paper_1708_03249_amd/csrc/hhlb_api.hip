@@ -504,15 +504,17 @@ hhlb_status cached_tables(const hhlb_channel &h, int N, int precision, const hhl
   return HHLB_OK;
 }
 
-// Tables of a large half-range class (Q > 16): the momenta in DevTables
-// (the aux kernels read them there) and the node-parallel stage's block.
+// Tables of a large class (Q > 16): the momenta in DevTables (the aux
+// kernels read them there) and the node-parallel stage's block.
 hhlb_status make_large_tables(const hhlb_channel &h, int N, const hhlb::Rule &r, hhlb::DevTables &d,
                               std::vector<char> &blob) {
   std::memset(&d, 0, sizeof(d));
   for (int k = 0; k < r.V; ++k) d.p[k] = r.p[k];
   d.inv_p0 = 1.0 / h.p0;
-  const int H = r.H, Q = h.Q;
-  const size_t nK = (size_t)H * H, nW = (size_t)H * (N + 1);
+  const int H = r.H, Q = h.Q, V = r.V;
+  const bool full = h.quad == HHLB_FULL_HERMITE;
+  const int rows = full ? V : H;
+  const size_t nK = (size_t)rows * rows, nW = (size_t)H * (N + 1);
   blob.assign(sizeof(hhlb::DevLarge) + sizeof(double) * (nK + nW), 0);
   hhlb::DevLarge &L = *(hhlb::DevLarge *)blob.data();
   double *KinT = (double *)(blob.data() + sizeof(hhlb::DevLarge));
@@ -520,6 +522,22 @@ hhlb_status make_large_tables(const hhlb_channel &h, int N, const hhlb::Rule &r,
   L.H = H;
   L.N = N;
   L.inv_p0 = 1.0 / h.p0;
+  if (full) {
+    // Eq. (H_Kk), transposed: KT[j V + k] = K[k][j]; no cross term.  HWs in
+    // the orthonormal form w_k h_l(z_k) = w_k He_l(z_k) / l! * sqrt(l!)
+    // (the table holds w_k He_l(z_k) / l!) for the H nodes with p > 0.
+    L.full = 1;
+    for (int l = 0; l <= hhlb::kNmaxLarge + 1; ++l) L.sq[l] = std::sqrt((double)l);
+    for (int j = 0; j < V; ++j)
+      for (int k = 0; k < V; ++k) KinT[(size_t)j * V + k] = r.K[(size_t)k * V + j];
+    long double sf = 1;
+    for (int l = 0; l <= N; ++l) {
+      if (l > 0) sf *= sqrtl((long double)l);
+      for (int k = 0; k < H; ++k)
+        HWs[(size_t)k * (N + 1) + l] = (double)((long double)r.HW[(size_t)k * Q + l] * sf);
+    }
+    return HHLB_OK;
+  }
   for (int k = 0; k < H; ++k) { L.ka[k] = r.ka[k]; L.kb[k] = r.kb[k]; }
   for (int l = 0; l <= N + 1 && l < (int)r.a.size(); ++l) { L.a[l] = (double)r.a[l]; L.mb[l] = (double)r.b[l]; }
   for (int j = 0; j < H; ++j)
@@ -681,13 +699,17 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
         std::string err;
         const bool large = h.Q > hhlb::kQmaxDev;
         if (large) {
-          // the node-parallel stage: half-range Gauss-Hermite, FP64, N <= 20
-          if (h.quad != HHLB_HALF_HERMITE || precision != HHLB_FP64 || N > hhlb::kNmaxLarge ||
-              h.Q > hhlb::kQmaxLarge)
+          // the node-parallel stage: FP64, N <= 20, half-range Gauss-Hermite
+          // with Q <= 256 per half or full-range Gauss-Hermite with Q <= 512
+          const bool ok_kind = (h.quad == HHLB_HALF_HERMITE && h.Q <= hhlb::kQmaxLarge) ||
+                               (h.quad == HHLB_FULL_HERMITE && h.Q <= 2 * hhlb::kQmaxLarge);
+          if (!ok_kind || precision != HHLB_FP64 || N > hhlb::kNmaxLarge)
             return fail(HHLB_E_UNSUPPORTED, "channel " + std::to_string(c) + ": Q > " +
                                                 std::to_string(hhlb::kQmaxDev) +
-                                                " runs the half-range Hermite model in FP64 with N <= 20 and Q <= " +
-                                                std::to_string(hhlb::kQmaxLarge));
+                                                " runs in FP64 with N <= 20: the half-range Hermite model with Q <= " +
+                                                std::to_string(hhlb::kQmaxLarge) +
+                                                " or the full-range Hermite model with Q <= " +
+                                                std::to_string(2 * hhlb::kQmaxLarge));
         }
         int st = hhlb::build_rule(h.quad, h.Q, h.p0, mc.rule, err);
         if (st) return fail(st, "channel " + std::to_string(c) + ": " + err);
@@ -968,7 +990,8 @@ void enqueue_class_stage(hhlb_solver *s, size_t ci, int stage, const void *inf, 
     hhlb::LargeArgs la;
     la.tl = (const hhlb::DevLarge *)(s->ws + mc.lbl_off);
     la.KinT = (const double *)(s->ws + mc.lbl_off + sizeof(hhlb::DevLarge));
-    la.HWs = la.KinT + (size_t)mc.rule.H * mc.rule.H;
+    const size_t rows = mc.quad == HHLB_FULL_HERMITE ? (size_t)mc.rule.V : (size_t)mc.rule.H;
+    la.HWs = la.KinT + rows * rows;
     la.p = ((const hhlb::DevTables *)(s->ws + s->o_tables) + ci)->p;
     la.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
     la.wins = (const hhlb::DevWindow *)(s->ws + mc.win_off);

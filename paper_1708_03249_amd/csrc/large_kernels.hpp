@@ -1,6 +1,7 @@
-// Node-parallel FP64 stage of the half-range model for large velocity sets
-// (17 <= Q <= 256 nodes per half, equilibrium order N <= 20): the paper's
-// HHLB(20;Q) models of the ballistic study (Sec. VI.D).  A lane holds one
+// Node-parallel FP64 stage for large velocity sets, equilibrium order
+// N <= 20: the half-range model with 17 <= Q <= 256 nodes per half and the
+// full-range model with 18 <= Q <= 512 nodes, the paper's HHLB(20;Q) and
+// HLB(20;Q) models of the ballistic study (Sec. VI.D).  A lane holds one
 // cell, as in stage_kernel_half, but the Q nodes of a half no longer fit a
 // lane's registers, so one stage runs as two kernels:
 //   large_cell_kernel: one wave per cell, lanes over nodes and then over
@@ -22,11 +23,14 @@ constexpr int kQmaxLarge = 256;   // nodes per half
 constexpr int kNmaxLarge = 20;    // equilibrium order
 constexpr int kCellStride = 48;   // doubles per cell in the cell-phase output
 
-// Tables of one large model class.  The transposed within-half block
-// KinT[j * H + k] = Kin[k][j] and HWs[k * (N+1) + l] follow the struct.
+// Tables of one large model class.  Half range: the transposed within-half
+// block KinT[j * H + k] = Kin[k][j]; full range (full = 1): the transposed
+// dense matrix KT[j * V + k] = K[k][j].  Then HWs[k * (N+1) + l] for the H
+// nodes with p > 0.
 struct DevLarge {
-  int32_t H, N, nm, pad;
+  int32_t H, N, nm, full;
   double inv_p0;
+  double sq[kNmaxLarge + 2];                       // sqrt(l), full range
   double ka[kQmaxLarge], kb[kQmaxLarge];
   double a[kNmaxLarge + 2], mb[kNmaxLarge + 2];   // monic recurrence
   double zm[kQmaxDev], wm[kQmaxDev];               // main rule (half-range Gauss-Hermite)
@@ -37,7 +41,7 @@ struct DevLarge {
 
 struct LargeArgs {
   const DevLarge *tl;
-  const double *KinT, *HWs, *p;   // p: V momenta
+  const double *KinT, *HWs, *p;   // KinT: KT in the full range; p: V momenta
   const DevChannel *chans;
   const DevWindow *wins;
   int32_t nwin, stage;
@@ -115,7 +119,20 @@ __global__ __launch_bounds__(256) void large_cell_kernel(LargeArgs A) {
     double Gp[kNmaxLarge + 1], Gm[kNmaxLarge + 1];
 #pragma unroll
     for (int l = 0; l <= kNmaxLarge; ++l) Gp[l] = Gm[l] = 0.0;
-    if (C.inv_Kn != 0.0) {
+    if (C.inv_Kn != 0.0 && tl->full) {
+      // full range (Sec. IV.A.3): G_l = E[He_l(X)], X ~ N(m u/p0, m T/p0^2),
+      // obeys G_{l+1} = ub G_l + l a G_{l-1} with a = m T/p0^2 - 1; kept as
+      // G_l / sqrt(l!) against HWs = w_k h_l(z_k) (h_l = He_l / sqrt(l!)).
+      // The mirrored half has h_l(-z) = (-1)^l h_l(z).
+      const double ub = u * tl->inv_p0, aa = T * tl->inv_p0 * tl->inv_p0 - 1.0;
+      Gp[0] = 1.0;
+      if (N >= 1) Gp[1] = ub;
+#pragma unroll
+      for (int l = 1; l < kNmaxLarge; ++l)
+        if (l + 1 <= N) Gp[l + 1] = (ub * Gp[l] + tl->sq[l] * aa * Gp[l - 1]) / tl->sq[l + 1];
+#pragma unroll
+      for (int l = 0; l <= kNmaxLarge; ++l) Gm[l] = (l & 1) ? -Gp[l] : Gp[l];
+    } else if (C.inv_Kn != 0.0) {
       const double sT = sqrt(T), s = sT * tl->inv_p0, y0 = -u / sT;
       auto accum = [&](double (&G)[kNmaxLarge + 1], double x, double wt) {
         double qm = 1.0, q = x - tl->a[0];
@@ -213,7 +230,7 @@ __global__ __launch_bounds__(256) void large_cell_kernel(LargeArgs A) {
 #endif
 constexpr int kNodeWaves = HHLB_LARGE_WAVES;
 constexpr int kTileNodes = 16;
-constexpr int kStepsPerWave = (kQmaxLarge / 4 + kNodeWaves - 1) / kNodeWaves;
+constexpr int kStepsPerWave = (kQmaxLarge / 4 + kNodeWaves - 1) / kNodeWaves;   // per chunk
 
 template <int ADV>
 __global__ __launch_bounds__(64 * kNodeWaves) __attribute__((amdgpu_waves_per_eu(HHLB_LARGE_OCC))) void large_node_kernel(LargeArgs A) {
@@ -236,9 +253,14 @@ __global__ __launch_bounds__(64 * kNodeWaves) __attribute__((amdgpu_waves_per_eu
   const bool inside = i >= 0 && i < Nx;
   const int ic = inside ? i : (i < 0 ? 0 : Nx - 1);      // clamped: loads stay in bounds
   const bool nfc = A.nfun > 1;
-  const double sg = hw ? -1.0 : 1.0;
+  const bool full = tl->full != 0;
+  const double sg = full ? 1.0 : (hw ? -1.0 : 1.0);      // K = blockdiag(Kin, -Kin) + cross (half)
   const int64_t rowh = C.off + (int64_t)hw * H * Nx;     // first row of this half
   const double *fin = A.in_f + rowh, *cin = nfc ? A.in_c + rowh : nullptr;
+  // rows of the contraction: the half's H rows, or all V = 2H (full range)
+  const int nrows = full ? 2 * H : H;
+  const double *rf = full ? A.in_f + C.off : fin;
+  const double *rc = full ? (nfc ? A.in_c + C.off : nullptr) : cin;
 
   // the tile's equilibrium rows HWs[k][0..N] (read after the first barrier)
   for (int t = threadIdx.x; t < kTileNodes * (kNmaxLarge + 1); t += 64 * kNodeWaves) {
@@ -247,41 +269,42 @@ __global__ __launch_bounds__(64 * kNodeWaves) __attribute__((amdgpu_waves_per_eu
   }
 
   // force: MFMA contraction over this wave's share of the rows
-  const int nsteps = (H + 3) / 4, spw = (nsteps + kNodeWaves - 1) / kNodeWaves;
+  const int nsteps = (nrows + 3) / 4, spw = (nsteps + kNodeWaves - 1) / kNodeWaves;
   const int s0 = wave * spw;
   const int nsw = nsteps - s0 < 0 ? 0 : (nsteps - s0 < spw ? nsteps - s0 : spw);
   const int kr = lane >> 4, jl = lane & 15;
-  const int an = kt0 + jl;                               // A row: node
+  const int an = kt0 + jl;                               // A row: node within the half
+  const int acol = full ? hw * H + an : an;              // its column of the table
   int bcell[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int il = win.i0 - kHalo + 16 * c + jl;
     bcell[c] = il < 0 ? 0 : (il >= Nx ? Nx - 1 : il);
   }
-  double av[kStepsPerWave];
-#pragma unroll
-  for (int t = 0; t < kStepsPerWave; ++t) {
-    const int row = 4 * (s0 + t) + kr;
-    const bool ok = t < nsw && row < H && an < H;
-    av[t] = A.KinT[ok ? (int64_t)row * H + an : 0];
-    if (!ok) av[t] = 0.0;
-  }
+  // chunks of kStepsPerWave steps (one chunk for the half range, Q <= 256;
+  // two for a full-range V up to 512), every load of a chunk issued before
+  // its first MFMA
   auto contract = [&](const double *src, dbl4 acc[4]) {
-    double bv[kStepsPerWave][4];
-#pragma unroll
-    for (int t = 0; t < kStepsPerWave; ++t) {
-      const int row = 4 * (s0 + t) + kr;
-      const bool ok = t < nsw && row < H;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[t][c] = ok ? src[(int64_t)row * Nx + bcell[c]] : 0.0;
-    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < nsw; t0 += kStepsPerWave) {   // wave-uniform
+      double av[kStepsPerWave], bv[kStepsPerWave][4];
 #pragma unroll
-    for (int t = 0; t < kStepsPerWave; ++t) {
-      if (t >= nsw) break;   // wave-uniform: MFMA runs with every lane active
+      for (int t = 0; t < kStepsPerWave; ++t) {
+        const int row = 4 * (s0 + t0 + t) + kr;
+        const bool ok = t0 + t < nsw && row < nrows;
+        const bool oka = ok && an < H;
+        av[t] = A.KinT[oka ? (int64_t)row * nrows + acol : 0];
+        if (!oka) av[t] = 0.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t][c], acc[c], 0, 0, 0);
+        for (int c = 0; c < 4; ++c) bv[t][c] = ok ? src[(int64_t)row * Nx + bcell[c]] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < kStepsPerWave; ++t) {
+        if (t0 + t >= nsw) break;   // wave-uniform: MFMA runs with every lane active
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t][c], acc[c], 0, 0, 0);
+      }
     }
   };
   // D[node 4r + kr][cell 16c + jl] sits in acc[c][r]; partial tiles to LDS,
@@ -304,14 +327,14 @@ __global__ __launch_bounds__(64 * kNodeWaves) __attribute__((amdgpu_waves_per_eu
   double kf[NG], kc[NG];
   {
     dbl4 accf[4];
-    contract(fin, accf);
+    contract(rf, accf);
     reduce(accf, kf);
   }
 #pragma unroll
   for (int q = 0; q < NG; ++q) kc[q] = 0.0;
   if (nfc) {   // uniform over the block
     dbl4 accc[4];
-    contract(cin, accc);
+    contract(rc, accc);
     reduce(accc, kc);
   }
   const int k0 = kt0 + wave * NG;                        // first node of this wave

@@ -140,7 +140,8 @@ void gauss_legendre01(int n, std::vector<ld> &tau, std::vector<ld> &lam) {
 }
 
 int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
-  if (Q < 1 || Q > kQmaxTables) { err = "Q out of range"; return HHLB_E_ARG; }
+  // V <= 2 kQmaxTables: Q per half for the half-range kinds, Q in all for the full range
+  if (Q < 1 || Q > (quad == kFull ? 2 * kQmaxTables : kQmaxTables)) { err = "Q out of range"; return HHLB_E_ARG; }
   if (!(p0 > 0) || !std::isfinite(p0)) { err = "p0 must be positive"; return HHLB_E_ARG; }
   if (quad == kFull && (Q % 2)) { err = "full-range Q must be even (no node at p = 0)"; return HHLB_E_ARG; }
   if (quad != kHalf && quad != kFull && quad != kHalfLag) { err = "unknown quadrature"; return HHLB_E_ARG; }

@@ -10,7 +10,7 @@ namespace hhlb {
 constexpr int kHalf = 0, kFull = 1, kHalfLag = 2;   // half Hermite, full Hermite, half Laguerre
 // half-range kinds share the kernels' split force matrix and equilibrium form
 inline bool half_range(int quad) { return quad != kFull; }
-constexpr int kQmaxTables = 256;  // largest Q the host builder accepts
+constexpr int kQmaxTables = 256;  // largest Q the host builder accepts (twice that for the full range)
 
 struct Rule {
   int quad = 0, Q = 0, V = 0, H = 0;

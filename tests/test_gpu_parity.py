@@ -138,6 +138,33 @@ def test_large_q_launch_configurations_identical():
         assert np.array_equal(outs[0][1], outs[k][1]), configs[k]
 
 
+def test_full_range_large_q_node_parallel():
+    """Full-range HLB(N;Q) with Q > 16 (the node-parallel stage, dense force
+    contraction over all V = Q rows): HLB(20;40) WENO-5 with chi on a
+    stretched grid with a perturbed start, HLB(19;24) upwind-3, and
+    HLB(20;100) collisionless from a smooth start."""
+    h = H()
+    chans = [h.Channel(quad=h.FULL_HERMITE, Q=40, N=20, Nx=70, adv=h.WENO5, transverse_dof=2,
+                       stretch_A=0.8, Kn=0.05, g=-0.5, T_left=1.0, T_right=1.6, dt=-0.5),
+             h.Channel(quad=h.FULL_HERMITE, Q=24, N=19, Nx=59, adv=h.UPWIND3, transverse_dof=0,
+                       Kn=0.2, g=0.3, T_left=1.2, T_right=1.0, dt=-0.5)]
+    _check(chans, 20, perturb=0.03, what="full range, large Q")
+    ch = h.Channel(quad=h.FULL_HERMITE, Q=100, N=20, Nx=40, adv=h.WENO5, transverse_dof=0,
+                   stretch_A=0.9, Kn=math.inf, g=-1.0, T_left=0.7, T_right=1.3, dt=-0.5)
+    _check([ch], 20, what="HLB(20;100)")
+
+
+def test_full_range_hlb_20_500_ballistic_setup():
+    """HLB(20;500), the paper's largest full-range model of the ballistic
+    study (Sec. VI.D), on its grid: Nx = 24, A = 0.99, Kn = inf, g_p = 1,
+    T_left = 1.4, T_right = 0.6, dt = 1e-4; 30 steps against the oracle from
+    the equilibrium at rest (smooth in p, as for HHLB(20;200))."""
+    h = H()
+    ch = h.Channel(quad=h.FULL_HERMITE, Q=500, N=20, Nx=24, adv=h.WENO5, transverse_dof=0,
+                   stretch_A=0.99, Kn=math.inf, g=-1.0, T_left=1.4, T_right=0.6, dt=1e-4)
+    _check([ch], 30, what="HLB(20;500)")
+
+
 def test_ballistic_hhlb_20_200_setup():
     """The paper's ballistic configuration (Sec. VI.D): HHLB(20;200), V = 400,
     Nx = 24, A = 0.99, Kn = inf, g = 0.1, T_left = 1.4, T_right = 0.6,

@@ -57,6 +57,27 @@ def test_host_equilibrium_laguerre_matches_oracle(Q, N, p0, u, T):
     np.testing.assert_allclose(g, go, rtol=0, atol=2e-15 * np.abs(go).max())
 
 
+@pytest.mark.parametrize("Q", [40, 100, 200])
+def test_host_full_range_large_q_tables_match_oracle(Q):
+    """Full-range HLB(20;Q) tables of the node-parallel path against the
+    oracle (monomial He_l up to Q = 64, its recurrence construction above).
+    K's columns span hundreds of decades (the entries of a node's column grow
+    like exp(z^2/2) while its populations shrink like exp(-z^2/2)), so each
+    column is compared relative to its own largest entry."""
+    p, w = H.nodes(H.FULL_HERMITE, Q)
+    K = H.force_matrix(H.FULL_HERMITE, Q)
+    po, wo, Ko, *_ = O.tables(O.FULL, Q)
+    np.testing.assert_allclose(p, po, rtol=4e-15, atol=0)
+    live = wo > 1e-280
+    np.testing.assert_allclose(w[live], wo[live], rtol=1e-12, atol=0)
+    colmax = np.abs(Ko).max(axis=0)
+    assert np.max(np.abs(K - Ko) / colmax) < 1e-13
+    for u, T in ((0.0, 1.0), (0.15, 1.6), (-0.2, 0.6)):
+        g = H.equilibrium(H.FULL_HERMITE, Q, 20, 1.0, u, T)
+        go = O.equilibrium(O.FULL, Q, 20, 1.0, u, T)
+        np.testing.assert_allclose(g, go, rtol=0, atol=2e-15 * np.abs(go).max())
+
+
 def test_mixed_forms_reject_laguerre():
     """The mixed-precision forms are built for the half-range Hermite model."""
     ch = H.Channel(quad=H.HALF_LAGUERRE, Q=4, p0=0.4)
@@ -95,15 +116,26 @@ def test_create_rejects_bad_arguments(bad):
 
 
 def test_create_unsupported_shape_and_null_calls():
-    # Q > 16 runs the node-parallel stage: FP64, half-range Hermite, N <= 20
+    # Q > 16 runs the node-parallel stage: FP64, N <= 20, half-range Hermite
+    # with Q <= 256 or full-range Hermite with Q <= 512
     st, _ = _create([H.Channel(Q=24, N=21)])
     assert st == -2
-    st, _ = _create([H.Channel(quad=H.FULL_HERMITE, Q=20)])
+    st, _ = _create([H.Channel(quad=H.FULL_HERMITE, Q=40, N=21)])
     assert st == -2
+    st, _ = _create([H.Channel(quad=H.HALF_LAGUERRE, Q=20)])
+    assert st == -2
+    st, _ = _create([H.Channel(Q=257)])
+    assert st in (-1, -2)
+    st, _ = _create([H.Channel(quad=H.FULL_HERMITE, Q=514)])
+    assert st in (-1, -2)
+    st, _ = _create([H.Channel(quad=H.FULL_HERMITE, Q=21)])
+    assert st == -1                              # odd full-range Q
     st, _ = _create([H.Channel(Q=24)], precision=H.MIXED_F32)
     assert st == -2
-    st, h = _create([H.Channel(Q=24)])
-    assert st == 0 and H.lib().hhlb_destroy(h) == 0
+    for ch in (H.Channel(Q=24), H.Channel(quad=H.FULL_HERMITE, Q=20), H.Channel(Q=256),
+               H.Channel(quad=H.FULL_HERMITE, Q=512)):
+        st, h = _create([ch])
+        assert st == 0 and H.lib().hhlb_destroy(h) == 0
     L = H.lib()
     assert L.hhlb_step(None, 1) == -1
     assert L.hhlb_workspace_bytes(None, None) == -1

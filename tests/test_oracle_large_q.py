@@ -112,3 +112,86 @@ def test_large_q_equilibrium_half_range_moments(Q, N):
         assert abs(got_m - ref_m) / sc < 1e-13, s
     with pytest.raises(ValueError):     # the recurrence rules keep orders N <= 20
         O.equilibrium(O.HALF, Q, 21, 1.0, u, T)
+
+
+# ---------------------------------------------------------------- full range
+
+@pytest.fixture
+def full_recurrence_everywhere():
+    old = O.set_qfmono(0)
+    yield
+    O.set_qfmono(old)
+
+
+@pytest.mark.parametrize("Q", [2, 8, 20, 40, 64])
+def test_full_range_recurrence_matches_monomial(Q, full_recurrence_everywhere):
+    """Where both full-range constructions apply (Q <= 64), the recurrence
+    one (Sturm roots, Eqs. H_wk and H_Kk through h_l = He_l / sqrt(l!)) gives
+    the monomial one's rule and force matrix."""
+    p, w, K, *_ = O.tables(O.FULL, Q)
+    old = O.set_qfmono(64)
+    try:
+        pm, wm, Km, *_ = O.tables(O.FULL, Q)
+    finally:
+        O.set_qfmono(old)
+    np.testing.assert_allclose(p, pm, rtol=2e-15, atol=1e-15)
+    np.testing.assert_allclose(w, wm, rtol=1e-14)
+    colmax = np.abs(Km).max(axis=0)
+    assert np.max(np.abs(K - Km) / colmax) < 1e-14
+
+
+@pytest.mark.parametrize("Q", [100, 150])
+def test_full_range_large_q_matches_numpy_hermegauss(Q):
+    """Sec. IV.A.1: the nodes are the roots of He_Q; with the normalised
+    weight the weights are numpy's hermegauss weights / sqrt(2 pi)."""
+    p, w, *_ = O.tables(O.FULL, Q)
+    xs, ws = np.polynomial.hermite_e.hermegauss(Q)
+    ws = ws / math.sqrt(2 * math.pi)
+    order = np.argsort(p)
+    np.testing.assert_allclose(p[order], xs, rtol=0, atol=1e-13)
+    live = ws > 1e-250
+    np.testing.assert_allclose(w[order][live], ws[live], rtol=1e-11)
+
+
+@pytest.mark.parametrize("Q", [100, 500])
+def test_full_range_large_q_exactness_and_force_moments(Q):
+    """Exactness against the Gaussian moments (s-1)!! to degree 2Q-1
+    (sampled), the force-moment identity sum_k p_k^s K_kk' = -s p_k'^{s-1}
+    for s < Q (sampled s and columns), and zero column sums relative to each
+    column's size (Sec. IV.A.4)."""
+    mp.mp.dps = 40
+    p, w, K, *_ = O.tables(O.FULL, Q)
+    z, wz = [mp.mpf(x) for x in p], [mp.mpf(x) for x in w]
+    for s in sorted(set([0, 1, 2, 3, 4, 10, 40, Q, 2 * Q - 2, 2 * Q - 1])):
+        got = mp.fsum(a * b ** s for a, b in zip(wz, z))
+        ref = mp.mpf(0) if s % 2 else mp.fac2(s - 1)
+        scale = mp.fsum(a * abs(b) ** s for a, b in zip(wz, z))
+        assert abs(got - ref) / scale < 3e-15 + 2e-17 * s, s
+    cols = sorted(set([0, 1, Q // 4, Q // 2 - 1, Q // 2, Q - 1]))
+    for s in sorted(set([0, 1, 2, 5, 20, Q // 2, Q - 1])):
+        worst = mp.mpf(0)
+        for kp in cols:
+            terms = [mp.mpf(p[k]) ** s * mp.mpf(K[k, kp]) for k in range(Q)]
+            lhs = mp.fsum(terms)
+            rhs = -s * mp.mpf(p[kp]) ** (s - 1) if s > 0 else mp.mpf(0)
+            worst = max(worst, abs(lhs - rhs) / (mp.fsum(abs(t) for t in terms) + abs(rhs)))
+        assert worst < 1e-14, s
+    assert np.max(np.abs(K.sum(axis=0)) / np.abs(K).sum(axis=0)) < 1e-15
+
+
+@pytest.mark.parametrize("Q", [100, 200])
+def test_full_range_large_q_equilibrium_moments(Q):
+    """Sec. IV.A.3: the moments s <= N of the order-N equilibrium equal the
+    Maxwellian's (mpmath quadrature), and N <= 20 is enforced above Q = 64."""
+    mp.mp.dps = 30
+    N, u, T = 20, 0.13, 1.6
+    g = O.equilibrium(O.FULL, Q, N, 1.0, u, T)
+    p, *_ = O.tables(O.FULL, Q)
+    maxw = lambda x: mp.exp(-(x - u) ** 2 / (2 * T)) / mp.sqrt(2 * mp.pi * T)
+    for s in range(N + 1):
+        ref = mp.quad(lambda x: x ** s * maxw(x), [-mp.inf, u, mp.inf])
+        sc = mp.quad(lambda x: abs(x) ** s * maxw(x), [-mp.inf, 0, mp.inf])
+        got = mp.fsum(mp.mpf(a) * mp.mpf(b) ** s for a, b in zip(g, p))
+        assert abs(got - ref) / sc < 1e-13, s
+    with pytest.raises(ValueError):
+        O.equilibrium(O.FULL, Q, 21, 1.0, u, T)
