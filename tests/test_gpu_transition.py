@@ -1,0 +1,84 @@
+"""Transition-regime convergence sweep (Sec. VI.E) as one batched solver:
+the full-range HLB(N;Q) and half-range HHLB(N;Q) models against reference
+profiles from HHLB(20;200), on the ballistic grid (Nx = 24, A = 0.99,
+dt = 1e-4, the 1-D gas) with Delta T = -0.4 (T_+ = 1.4, T_- = 0.6), for
+the paper's six cases (g_p, Kn) in {0.1, 1} x {0.1, 0.5, 1}.  The measure is
+Eq. (epsmax) with the reference profiles in place of the closed forms.
+
+What the paper reports and this test checks:
+  - HLB(20;500) passes the 1 % test for (g, Kn) in {(0.1, 0.1), (0.1, 0.5),
+    (1, 0.1)} and fails it for {(0.1, 1), (1, 0.5), (1, 1)};
+  - the HLB error decreases as Q grows (here Q = 100 -> 500);
+  - at a fixed number of velocities the HLB error is larger than the HHLB
+    one (here 100 velocities: HLB(20;100) against HHLB(20;50)).
+Four model classes of uneven V (400, 500, 100, 100) run in one solver on
+class streams: the batched form of the sweep."""
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+from oracle import ballistic as B  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+COMBOS = [(0.1, 0.1), (0.1, 0.5), (0.1, 1.0), (1.0, 0.1), (1.0, 0.5), (1.0, 1.0)]
+PAPER_PASS_AT_500 = {(0.1, 0.1), (0.1, 0.5), (1.0, 0.1)}
+DT, T_END, CHUNK = 1e-4, 15.0, 50_000
+D_T = -0.4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_transition_regime_convergence_pattern():
+    import torch
+    import paper_1708_03249_amd as H
+    models = [("HHLB(20;200)", H.HALF_HERMITE, 200), ("HLB(20;500)", H.FULL_HERMITE, 500),
+              ("HLB(20;100)", H.FULL_HERMITE, 100), ("HHLB(20;50)", H.HALF_HERMITE, 50)]
+    chans = [H.Channel(quad=quad, Q=Q, N=20, Nx=24, adv=H.WENO5, transverse_dof=0, stretch_A=0.99,
+                       Kn=kn, g=-gp, T_left=1 - D_T, T_right=1 + D_T, dt=DT)
+             for _, quad, Q in models for gp, kn in COMBOS]
+    s = H.Solver(chans)
+    try:
+        s.set_tuning(class_streams=1)
+        s.init_equilibrium()
+        nsteps = int(round(T_END / DT))
+        done, t0, prev = 0, time.time(), None
+        while done < nsteps:
+            k = min(CHUNK, nsteps - done)
+            s.step(k)
+            done += k
+            n, u, T = (a.cpu().numpy() for a in s.moments())
+            _, mass, bad = s.diagnostics()
+            assert int(bad.cpu().item()) == 0
+            prof = [(n[s.cells[c]:s.cells[c + 1]], T[s.cells[c]:s.cells[c + 1]]) for c in range(len(chans))]
+            eps = {}
+            for m, (name, _, _) in enumerate(models[1:], start=1):
+                eps[name] = [max(B.eps(list(prof[m * 6 + j][0]), list(prof[j][0])),
+                                 B.eps(list(prof[m * 6 + j][1]), list(prof[j][1]))) for j in range(6)]
+            ref = np.concatenate([np.concatenate(prof[j]) for j in range(6)])
+            drift = np.inf if prev is None else float(np.abs(ref - prev).max())
+            prev = ref
+            print(f"[transition] t={done * DT:5.1f} ({time.time() - t0:5.1f}s) reference drift {drift:.1e}; "
+                  + "; ".join(f"{k} " + " ".join(f"{100 * e:.2f}" for e in v) for k, v in eps.items()),
+                  flush=True)
+        mass = mass.cpu().numpy()
+    finally:
+        s.close()
+    np.testing.assert_allclose(mass, 1.0, rtol=0, atol=1e-9)
+    assert drift < 1e-4                       # the reference profiles are steady
+    for j, combo in enumerate(COMBOS):
+        e500, e100, ehh50 = eps["HLB(20;500)"][j], eps["HLB(20;100)"][j], eps["HHLB(20;50)"][j]
+        assert (e500 < 0.01) == (combo in PAPER_PASS_AT_500), (combo, e500)
+        assert e500 < e100, (combo, e100, e500)
+        assert ehh50 < e100, (combo, ehh50, e100)
