@@ -239,6 +239,47 @@ hhlb_status hhlb_destroy(hhlb_solver *s);
  * call on the same thread. */
 const char *hhlb_last_error(void);
 
+/* ---- mixed-quadrature velocity space (App. A), homogeneous gas ---------- */
+
+/* One axis of a direct-product velocity set (App. A.1): quadrature kind
+ * (HHLB_HALF_HERMITE, HHLB_FULL_HERMITE or HHLB_HALF_LAGUERRE) and order Q,
+ * equilibrium order N (0 <= N < Q, N <= 20) and momentum scale p0 > 0.
+ * The axis has V_a = 2Q velocities (half range) or Q (full range, Q even);
+ * V_a <= 32, and the product V = prod V_a <= 512 (else HHLB_E_UNSUPPORTED). */
+typedef struct {
+  int32_t quad, Q, N;
+  double p0;
+} hhlb_axis;
+
+/* App. A.1: the product velocity set of d = 2 or 3 axes, velocity
+ * v = (i V_y + j) V_z + k (x index slowest).  p_out[a*V + v] (d*V host
+ * doubles, caller-owned) and w_out[V] (the product of the axis weights). */
+hhlb_status hhlb_multi_nodes(const hhlb_axis *axes, int32_t d, double *p_out, double *w_out);
+
+/* Bytes of device workspace hhlb_multi_rhs / hhlb_multi_step need for npts
+ * points: the tables (uploaded by each call) and two RK stage copies of f. */
+hhlb_status hhlb_multi_workspace_bytes(const hhlb_axis *axes, int32_t d, int64_t npts, size_t *bytes);
+
+/* Right-hand side of Eq. (boltz_multi_k) without advection (App. A), for
+ * npts independent points:
+ *   L_v = - sum_a F_a (K_a f)_v - (f_v - feq_v) n / Kn,
+ * K_a the axis' matrix of Eq. (H_Kk) / (hh_Kk), feq = n g_x g_y [g_z] the
+ * product of the axes' truncated equilibria (Eqs. H_gk / hh_gk) at the
+ * point's n, u, T (App. A.2; d n T = sum |p - u|^2 f, m = 1).
+ * f_dev, L_dev: device FP64, point-major [npts][V]; F: d host doubles (the
+ * acceleration); Kn > 0 or +INFINITY (no collisions); work_dev: device
+ * workspace of at least hhlb_multi_workspace_bytes(..., npts) bytes.
+ * Asynchronous on hip_stream (a hipStream_t, NULL = default stream). */
+hhlb_status hhlb_multi_rhs(const hhlb_axis *axes, int32_t d, const double *f_dev, int64_t npts,
+                           const double *F, double Kn, double *L_dev, void *work_dev, size_t work_bytes,
+                           void *hip_stream);
+
+/* n_steps TVD RK-3 steps (Eq. rk3) of the same system with time step dt,
+ * in place on f_dev.  Arguments as for hhlb_multi_rhs. */
+hhlb_status hhlb_multi_step(const hhlb_axis *axes, int32_t d, double *f_dev, int64_t npts, const double *F,
+                            double Kn, double dt, int32_t n_steps, void *work_dev, size_t work_bytes,
+                            void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

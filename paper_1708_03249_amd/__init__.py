@@ -83,6 +83,31 @@ class Channel:
                          self.p0, self.dt)
 
 
+class _CAxis(ctypes.Structure):
+    _fields_ = [("quad", ctypes.c_int32), ("Q", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("p0", ctypes.c_double)]
+
+
+@dataclass
+class Axis:
+    """One axis of a mixed-quadrature velocity set (App. A)."""
+    quad: int = HALF_HERMITE
+    Q: int = 4
+    N: int = -1          # < 0: min(20, Q - 1)
+    p0: float = 1.0
+
+    @property
+    def V(self) -> int:
+        return self.Q if self.quad == FULL_HERMITE else 2 * self.Q
+
+
+def _axes(axes):
+    arr = (_CAxis * len(axes))()
+    for a, ax in enumerate(axes):
+        arr[a] = _CAxis(ax.quad, ax.Q, ax.N if ax.N >= 0 else min(20, ax.Q - 1), ax.p0)
+    return arr
+
+
 _lib = None
 
 
@@ -117,6 +142,14 @@ def lib():
         L.hhlb_set_tuning.argtypes = [vp, ctypes.POINTER(_CTuning)]
         L.hhlb_get_tuning.argtypes = [vp, ctypes.POINTER(_CTuning)]
         L.hhlb_autotune.argtypes = [vp, i32, ctypes.POINTER(_CTuning)]
+        ap = ctypes.POINTER(_CAxis)
+        L.hhlb_multi_nodes.argtypes = [ap, i32, dp, dp]
+        L.hhlb_multi_workspace_bytes.argtypes = [ap, i32, i64, ctypes.POINTER(ctypes.c_size_t)]
+        L.hhlb_multi_rhs.argtypes = [ap, i32, vp, i64, dp, ctypes.c_double, vp, vp, ctypes.c_size_t, vp]
+        L.hhlb_multi_step.argtypes = [ap, i32, vp, i64, dp, ctypes.c_double, ctypes.c_double, i32, vp,
+                                      ctypes.c_size_t, vp]
+        for name in ("hhlb_multi_nodes", "hhlb_multi_workspace_bytes", "hhlb_multi_rhs", "hhlb_multi_step"):
+            getattr(L, name).restype = ctypes.c_int32
         for name in ("hhlb_nodes", "hhlb_force_matrix", "hhlb_equilibrium", "hhlb_create",
                      "hhlb_workspace_bytes", "hhlb_bind_workspace", "hhlb_state_offsets",
                      "hhlb_time_steps", "hhlb_set_state", "hhlb_init_equilibrium", "hhlb_step",
@@ -157,6 +190,49 @@ def equilibrium(quad: int, Q: int, N: int, n: float, u: float, T: float, p0: flo
     g = np.zeros(V)
     _check(lib().hhlb_equilibrium(quad, Q, N, p0, n, u, T, _dptr(g)))
     return g
+
+
+def multi_nodes(axes):
+    """App. A.1: momenta (d, V) and product weights (V,) of a mixed set."""
+    V = int(np.prod([a.V for a in axes]))
+    p, w = np.zeros((len(axes), V)), np.zeros(V)
+    _check(lib().hhlb_multi_nodes(_axes(axes), len(axes), _dptr(p), _dptr(w)))
+    return p, w
+
+
+class MultiSolver:
+    """The homogeneous mixed-quadrature system of App. A for npts points on
+    one GPU: f is a (npts, V) float64 CUDA tensor the caller owns; the
+    workspace (tables and two RK stage copies) comes from torch."""
+
+    def __init__(self, axes, npts, F, Kn, stream=None):
+        import torch
+        self.axes, self.npts = list(axes), int(npts)
+        self.F = np.ascontiguousarray(np.asarray(F, dtype=np.float64))
+        assert self.F.shape == (len(self.axes),)
+        self.Kn = float(Kn)
+        self.V = int(np.prod([a.V for a in self.axes]))
+        self._ax = _axes(self.axes)
+        nb = ctypes.c_size_t()
+        _check(lib().hhlb_multi_workspace_bytes(self._ax, len(self.axes), self.npts, ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream or torch.cuda.current_stream()
+
+    def _f(self, f):
+        import torch
+        assert f.dtype == torch.float64 and f.is_cuda and f.is_contiguous() and f.numel() == self.npts * self.V
+        return ctypes.c_void_p(f.data_ptr())
+
+    def rhs(self, f, L):
+        _check(lib().hhlb_multi_rhs(self._ax, len(self.axes), self._f(f), self.npts, _dptr(self.F), self.Kn,
+                                    self._f(L), ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                    ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def step(self, f, dt, n_steps):
+        _check(lib().hhlb_multi_step(self._ax, len(self.axes), self._f(f), self.npts, _dptr(self.F), self.Kn,
+                                     float(dt), int(n_steps), ctypes.c_void_p(self.ws.data_ptr()),
+                                     self.ws_bytes, ctypes.c_void_p(self.stream.cuda_stream)))
 
 
 class Solver:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -15,6 +16,7 @@
 #include "../../include/hhlb.h"
 #include "large_kernels.hpp"
 #include "launch.hpp"
+#include "multi_kernels.hpp"
 #include "step_kernels.hpp"
 #include "tables.hpp"
 
@@ -1363,6 +1365,218 @@ hhlb_status hhlb_launch_info(const hhlb_solver *s, int32_t *launches_per_stage, 
 
 hhlb_status hhlb_destroy(hhlb_solver *s) {
   delete s;
+  return HHLB_OK;
+}
+
+}  // extern "C"
+
+// ---- mixed-quadrature velocity space (App. A), homogeneous gas ------------
+
+namespace {
+
+// Tables of one product set: DevMulti and its trailing doubles, built once
+// per set of axes and kept for the life of the process (the uploads read
+// them asynchronously).
+struct MultiSet {
+  std::vector<char> blob;
+  int d = 0, V = 0;
+};
+
+std::mutex g_multi_mu;
+std::map<std::string, std::shared_ptr<const MultiSet>> g_multi_cache;
+
+hhlb_status multi_set(const hhlb_axis *axes, int32_t d, std::shared_ptr<const MultiSet> &out) {
+  if (!axes) return fail(HHLB_E_ARG, "null axes");
+  if (d < 2 || d > hhlb::kMultiAxes) return fail(HHLB_E_ARG, "d must be 2 or 3");
+  std::string key = std::to_string(d);
+  for (int a = 0; a < d; ++a) {
+    char b[96];
+    std::snprintf(b, sizeof b, "|%d,%d,%d,%a", axes[a].quad, axes[a].Q, axes[a].N, axes[a].p0);
+    key += b;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    auto it = g_multi_cache.find(key);
+    if (it != g_multi_cache.end()) { out = it->second; return HHLB_OK; }
+  }
+  try {
+    std::vector<hhlb::Rule> rules(d);
+    int V = 1;
+    for (int a = 0; a < d; ++a) {
+      const hhlb_axis &x = axes[a];
+      const std::string ax = "axis " + std::to_string(a) + ": ";
+      if (x.quad != HHLB_HALF_HERMITE && x.quad != HHLB_FULL_HERMITE && x.quad != HHLB_HALF_LAGUERRE)
+        return fail(HHLB_E_ARG, ax + "unknown quadrature");
+      if (x.N < 0 || x.N >= x.Q) return fail(HHLB_E_ARG, ax + "N must satisfy 0 <= N < Q");
+      std::string err;
+      int st = hhlb::build_rule(x.quad, x.Q, x.p0, rules[a], err);
+      if (st) return fail(st, ax + err);
+      if (x.N > hhlb::kNmaxLarge || rules[a].V > hhlb::kMultiVaxis)
+        return fail(HHLB_E_UNSUPPORTED, ax + "needs N <= 20 and at most 32 velocities");
+      V *= rules[a].V;
+    }
+    if (V > hhlb::kMultiVmax) return fail(HHLB_E_UNSUPPORTED, "the product set has more than 512 velocities");
+    hhlb::DevMulti hdr;
+    std::memset(&hdr, 0, sizeof hdr);
+    hdr.d = d;
+    hdr.V = V;
+    std::vector<double> tail;
+    int stride = V;
+    for (int a = 0; a < d; ++a) {
+      const hhlb::Rule &r = rules[a];
+      stride /= r.V;
+      hdr.Va[a] = r.V;
+      hdr.stride[a] = stride;
+      hdr.p_off[a] = (int32_t)tail.size();
+      tail.insert(tail.end(), r.p.begin(), r.p.end());
+      hdr.k_off[a] = (int32_t)tail.size();
+      tail.insert(tail.end(), r.K.begin(), r.K.end());
+      // the axis' equilibrium tables: those of the 1-D large-velocity-set path
+      hhlb_channel h;
+      std::memset(&h, 0, sizeof h);
+      h.quad = axes[a].quad;
+      h.Q = axes[a].Q;
+      h.p0 = axes[a].p0;
+      hhlb::DevTables dt;
+      std::vector<char> lb;
+      int st = make_large_tables(h, axes[a].N, r, dt, lb);
+      if (st) return st;
+      std::memcpy(&hdr.ax[a], lb.data(), sizeof(hhlb::DevLarge));
+      const size_t rows = axes[a].quad == HHLB_FULL_HERMITE ? (size_t)r.V : (size_t)r.H;
+      const double *hws = (const double *)(lb.data() + sizeof(hhlb::DevLarge)) + rows * rows;
+      hdr.hw_off[a] = (int32_t)tail.size();
+      tail.insert(tail.end(), hws, hws + (size_t)r.H * (axes[a].N + 1));
+    }
+    // packed per-axis indices of every velocity (v = (i V_y + j) V_z + k)
+    hdr.idx_off = (int32_t)tail.size();
+    std::vector<int32_t> idx(V, 0);
+    for (int v = 0; v < V; ++v)
+      for (int a = 0; a < d; ++a) idx[v] |= ((v / hdr.stride[a]) % hdr.Va[a]) << (8 * a);
+    auto ms = std::make_shared<MultiSet>();
+    ms->blob.resize(sizeof hdr + sizeof(double) * tail.size() + sizeof(int32_t) * V);
+    std::memcpy(ms->blob.data(), &hdr, sizeof hdr);
+    std::memcpy(ms->blob.data() + sizeof hdr, tail.data(), sizeof(double) * tail.size());
+    std::memcpy(ms->blob.data() + sizeof hdr + sizeof(double) * tail.size(), idx.data(), sizeof(int32_t) * V);
+    ms->d = d;
+    ms->V = V;
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    out = g_multi_cache.emplace(key, ms).first->second;
+  } catch (...) {
+    return fail(HHLB_E_NOMEM, "allocation failed");
+  }
+  return HHLB_OK;
+}
+
+size_t multi_state_bytes(int64_t npts, int V) { return align256((size_t)npts * (size_t)V * sizeof(double)); }
+
+hhlb_status multi_launch_checks(const MultiSet &ms, const void *f, int64_t npts, const double *F, double Kn,
+                                const void *work, size_t work_bytes, size_t need) {
+  if (npts < 0) return fail(HHLB_E_ARG, "npts must be >= 0");
+  if ((!f && npts > 0) || !F || !work) return fail(HHLB_E_ARG, "null pointer");
+  if (!(Kn > 0)) return fail(HHLB_E_ARG, "Kn must be > 0 (+INFINITY: no collisions)");
+  for (int a = 0; a < ms.d; ++a)
+    if (!std::isfinite(F[a])) return fail(HHLB_E_ARG, "F must be finite");
+  if (work_bytes < need) return fail(HHLB_E_ARG, "workspace too small");
+  return HHLB_OK;
+}
+
+hhlb::MultiArgs multi_args(const MultiSet &ms, void *work, int64_t npts, const double *F, double Kn) {
+  hhlb::MultiArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.tm = (const hhlb::DevMulti *)work;
+  a.tab = (const double *)((const char *)work + sizeof(hhlb::DevMulti));
+  a.npts = npts;
+  for (int k = 0; k < ms.d; ++k) a.F[k] = F[k];
+  a.inv_Kn = std::isinf(Kn) ? 0.0 : 1.0 / Kn;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+hhlb_status hhlb_multi_nodes(const hhlb_axis *axes, int32_t d, double *p_out, double *w_out) {
+  if (!p_out || !w_out) return fail(HHLB_E_ARG, "null output pointer");
+  std::shared_ptr<const MultiSet> ms;
+  int st = multi_set(axes, d, ms);
+  if (st) return st;
+  const hhlb::DevMulti &h = *(const hhlb::DevMulti *)ms->blob.data();
+  const double *tab = (const double *)(ms->blob.data() + sizeof(hhlb::DevMulti));
+  for (int v = 0; v < h.V; ++v) {
+    w_out[v] = 1.0;
+    for (int a = 0; a < d; ++a) p_out[(size_t)a * h.V + v] = tab[h.p_off[a] + (v / h.stride[a]) % h.Va[a]];
+  }
+  // the product of the axis weights
+  try {
+    for (int a = 0; a < d; ++a) {
+      hhlb::Rule r;
+      std::string err;
+      st = hhlb::build_rule(axes[a].quad, axes[a].Q, axes[a].p0, r, err);
+      if (st) return fail(st, err);
+      for (int v = 0; v < h.V; ++v) w_out[v] *= r.wv[(v / h.stride[a]) % h.Va[a]];
+    }
+  } catch (...) {
+    return fail(HHLB_E_NOMEM, "allocation failed");
+  }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_multi_workspace_bytes(const hhlb_axis *axes, int32_t d, int64_t npts, size_t *bytes) {
+  if (!bytes) return fail(HHLB_E_ARG, "null output pointer");
+  if (npts < 0) return fail(HHLB_E_ARG, "npts must be >= 0");
+  std::shared_ptr<const MultiSet> ms;
+  int st = multi_set(axes, d, ms);
+  if (st) return st;
+  *bytes = align256(ms->blob.size()) + 2 * multi_state_bytes(npts, ms->V);
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_multi_rhs(const hhlb_axis *axes, int32_t d, const double *f_dev, int64_t npts,
+                           const double *F, double Kn, double *L_dev, void *work_dev, size_t work_bytes,
+                           void *hip_stream) {
+  std::shared_ptr<const MultiSet> ms;
+  int st = multi_set(axes, d, ms);
+  if (st) return st;
+  st = multi_launch_checks(*ms, f_dev, npts, F, Kn, work_dev, work_bytes, align256(ms->blob.size()));
+  if (st) return st;
+  if (!L_dev && npts > 0) return fail(HHLB_E_ARG, "null pointer");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipMemcpyAsync(work_dev, ms->blob.data(), ms->blob.size(), hipMemcpyHostToDevice, s));
+  hhlb::MultiArgs a = multi_args(*ms, work_dev, npts, F, Kn);
+  a.in = f_dev;
+  a.out = L_dev;
+  a.rhs_only = 1;
+  hhlb::launch_multi(a, s);
+  HIP_TRY(hipGetLastError());
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_multi_step(const hhlb_axis *axes, int32_t d, double *f_dev, int64_t npts, const double *F,
+                            double Kn, double dt, int32_t n_steps, void *work_dev, size_t work_bytes,
+                            void *hip_stream) {
+  std::shared_ptr<const MultiSet> ms;
+  int st = multi_set(axes, d, ms);
+  if (st) return st;
+  const size_t tb = align256(ms->blob.size()), sb = multi_state_bytes(npts, ms->V);
+  st = multi_launch_checks(*ms, f_dev, npts, F, Kn, work_dev, work_bytes, tb + 2 * sb);
+  if (st) return st;
+  if (n_steps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(HHLB_E_ARG, "need n_steps >= 0 and dt > 0");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipMemcpyAsync(work_dev, ms->blob.data(), ms->blob.size(), hipMemcpyHostToDevice, s));
+  double *y1 = (double *)((char *)work_dev + tb), *y2 = (double *)((char *)work_dev + tb + sb);
+  hhlb::MultiArgs a = multi_args(*ms, work_dev, npts, F, Kn);
+  a.dt = dt;
+  for (int k = 0; k < n_steps; ++k) {
+    // Eq. (rk3): y1 = y + dt L[y]; y2 = 3/4 y + 1/4 (y1 + dt L[y1]);
+    // y+ = 1/3 y + 2/3 (y2 + dt L[y2])
+    a.in = f_dev; a.base = nullptr; a.out = y1; a.a_base = 0.0; a.b_stage = 1.0;
+    hhlb::launch_multi(a, s);
+    a.in = y1; a.base = f_dev; a.out = y2; a.a_base = 0.75; a.b_stage = 0.25;
+    hhlb::launch_multi(a, s);
+    a.in = y2; a.base = f_dev; a.out = f_dev; a.a_base = 1.0 / 3.0; a.b_stage = 2.0 / 3.0;
+    hhlb::launch_multi(a, s);
+  }
+  HIP_TRY(hipGetLastError());
   return HHLB_OK;
 }
 

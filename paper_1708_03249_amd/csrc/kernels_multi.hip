@@ -1,0 +1,138 @@
+// The mixed-quadrature (App. A) velocity-space stage kernel and its launcher.
+#include "multi_kernels.hpp"
+
+namespace hhlb {
+
+__global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
+  __shared__ double s_f[kMultiWaves][kMultiVmax];
+  __shared__ double s_g[kMultiWaves][kMultiAxes * kMultiVaxis];
+  __shared__ double s_K[kMultiAxes * kMultiVaxis * kMultiVaxis];   // the axes' K_a, row-major
+  __shared__ double s_p[kMultiAxes * kMultiVaxis];
+  __shared__ int32_t s_idx[kMultiVmax];   // packed per-axis indices of each velocity
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const DevMulti *tm = A.tm;
+  const int d = tm->d, V = tm->V;
+  // the block stages the axes' tables (every wave takes this barrier)
+#pragma unroll
+  for (int a = 0; a < kMultiAxes; ++a) {
+    if (a >= d) break;
+    const int Va = tm->Va[a];
+    for (int t = threadIdx.x; t < Va * Va; t += 64 * kMultiWaves)
+      s_K[a * kMultiVaxis * kMultiVaxis + t] = A.tab[tm->k_off[a] + t];
+    if ((int)threadIdx.x < Va) s_p[a * kMultiVaxis + threadIdx.x] = A.tab[tm->p_off[a] + threadIdx.x];
+  }
+  {
+    const int32_t *gi = (const int32_t *)(A.tab + tm->idx_off);
+    for (int t = threadIdx.x; t < V; t += 64 * kMultiWaves) s_idx[t] = gi[t];
+  }
+  __syncthreads();
+  const int64_t pt = (int64_t)blockIdx.x * kMultiWaves + wave;
+  if (pt >= A.npts) return;   // wave-uniform; only wave-level barriers follow
+  const double *y = A.in + pt * V;
+  double *sf = s_f[wave], *sg = s_g[wave];
+  constexpr int KT = kMultiVmax / 64;
+  // per-axis indices of this lane's velocities (v = (i V_y + j) V_z + k)
+  int ia[KT][kMultiAxes];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int v = lane + 64 * t, w = v < V ? s_idx[v] : 0;
+#pragma unroll
+    for (int a = 0; a < kMultiAxes; ++a) ia[t][a] = (w >> (8 * a)) & 0xff;
+  }
+
+  // populations (fixed trip count: the loads issue together) and moments
+  double fv[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int v = lane + 64 * t;
+    fv[t] = v < V ? y[v] : 0.0;
+    if (v < V) sf[v] = fv[t];
+  }
+  double n = 0.0, mom[kMultiAxes] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int v = lane + 64 * t;
+    if (v < V) {
+      n += fv[t];
+#pragma unroll
+      for (int a = 0; a < kMultiAxes; ++a)
+        if (a < d) mom[a] += s_p[a * kMultiVaxis + ia[t][a]] * fv[t];
+    }
+  }
+  n = wave_sum(n);
+  double u[kMultiAxes] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < kMultiAxes; ++a)
+    if (a < d) u[a] = wave_sum(mom[a]) / n;
+  double c2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int v = lane + 64 * t;
+    if (v < V) {
+      double q = 0.0;
+#pragma unroll
+      for (int a = 0; a < kMultiAxes; ++a)
+        if (a < d) {
+          const double c = s_p[a * kMultiVaxis + ia[t][a]] - u[a];
+          q += c * c;
+        }
+      c2 += q * fv[t];
+    }
+  }
+  const double T = wave_sum(c2) / (d * n);
+
+  // per-axis 1-D equilibrium factors g_a[i] (App. A.2) into LDS; a runtime
+  // loop over the axes keeps one inlined copy of axis_coeffs (code size)
+  if (A.inv_Kn != 0.0) {
+#pragma unroll 1
+    for (int a = 0; a < d; ++a) {
+      const double ua = a == 0 ? u[0] : (a == 1 ? u[1] : u[2]);
+      double Gp[kNmaxLarge + 1], Gm[kNmaxLarge + 1];
+      axis_coeffs(&tm->ax[a], ua, T, lane, Gp, Gm);
+      const int Va = tm->Va[a], H = Va / 2, N = tm->ax[a].N;
+      if (lane < Va) {
+        const int k = lane < H ? lane : lane - H;
+        const double *hw = A.tab + tm->hw_off[a] + k * (N + 1);
+        double gp = 0.0, gm = 0.0;
+#pragma unroll
+        for (int l = 0; l <= kNmaxLarge; ++l)
+          if (l <= N) {
+            gp = fma(hw[l], Gp[l], gp);
+            gm = fma(hw[l], Gm[l], gm);
+          }
+        sg[a * kMultiVaxis + lane] = lane < H ? gp : gm;
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  // force contractions, BGK and the RK-3 combination (runtime loops: the
+  // populations come back from LDS)
+  const double F0 = A.F[0], F1 = A.F[1], F2 = A.F[2];
+  for (int v = lane; v < V; v += 64) {
+    const double fvv = sf[v];
+    const int w = s_idx[v];
+    double force = 0.0, g = n;
+    for (int a = 0; a < d; ++a) {
+      const int st = tm->stride[a], Va = tm->Va[a];
+      const int i = (w >> (8 * a)) & 0xff, v0 = v - i * st;
+      const double *K = s_K + a * kMultiVaxis * kMultiVaxis + i * Va;
+      double acc = 0.0;
+      for (int ip = 0; ip < Va; ++ip) acc = fma(K[ip], sf[v0 + ip * st], acc);
+      force = fma(a == 0 ? F0 : (a == 1 ? F1 : F2), acc, force);
+      g *= sg[a * kMultiVaxis + i];
+    }
+    double L = -force;
+    if (A.inv_Kn != 0.0) L -= (fvv - g) * (n * A.inv_Kn);
+    const int64_t o = pt * V + v;
+    A.out[o] = A.rhs_only ? L : A.a_base * (A.a_base != 0.0 ? A.base[o] : 0.0) + A.b_stage * (fvv + A.dt * L);
+  }
+}
+
+void launch_multi(const MultiArgs &a, hipStream_t s) {
+  if (a.npts <= 0) return;
+  const int64_t blocks = (a.npts + kMultiWaves - 1) / kMultiWaves;
+  hipLaunchKernelGGL(multi_kernel, dim3((unsigned)blocks), dim3(64 * kMultiWaves), 0, s, a);
+}
+
+}  // namespace hhlb

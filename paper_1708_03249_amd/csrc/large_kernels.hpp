@@ -57,6 +57,72 @@ struct LargeArgs {
   int32_t xcd_map;                // 1: the blocks of a window run on one XCD
 };
 
+// Equilibrium coefficients of one axis at (u, T) for a whole wave (every
+// lane returns the same G^+_l and G^-_l, l <= N): Sec. IV.B.3 by the change
+// of variables, the main rule and the correction spread over the lanes and
+// collected by wave sums; for the full range the closed-form recurrence of
+// Sec. IV.A.3.  Called by every lane of the wave.
+__device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double T, int lane,
+                                            double (&Gp)[kNmaxLarge + 1], double (&Gm)[kNmaxLarge + 1]) {
+  const int N = tl->N;
+#pragma unroll
+  for (int l = 0; l <= kNmaxLarge; ++l) Gp[l] = Gm[l] = 0.0;
+  if (tl->full) {
+    // full range (Sec. IV.A.3): G_l = E[He_l(X)], X ~ N(m u/p0, m T/p0^2),
+    // obeys G_{l+1} = ub G_l + l a G_{l-1} with a = m T/p0^2 - 1; kept as
+    // G_l / sqrt(l!) against HWs = w_k h_l(z_k) (h_l = He_l / sqrt(l!)).
+    // The mirrored half has h_l(-z) = (-1)^l h_l(z).
+    const double ub = u * tl->inv_p0, aa = T * tl->inv_p0 * tl->inv_p0 - 1.0;
+    Gp[0] = 1.0;
+    if (N >= 1) Gp[1] = ub;
+#pragma unroll
+    for (int l = 1; l < kNmaxLarge; ++l)
+      if (l + 1 <= N) Gp[l + 1] = (ub * Gp[l] + tl->sq[l] * aa * Gp[l - 1]) / tl->sq[l + 1];
+#pragma unroll
+    for (int l = 0; l <= kNmaxLarge; ++l) Gm[l] = (l & 1) ? -Gp[l] : Gp[l];
+    return;
+  }
+  const double sT = sqrt(T), s = sT * tl->inv_p0, y0 = -u / sT;
+  auto accum = [&](double (&G)[kNmaxLarge + 1], double x, double wt) {
+    double qm = 1.0, q = x - tl->a[0];
+    G[0] += wt;
+    if (N >= 1) G[1] += wt * q;
+#pragma unroll
+    for (int l = 1; l < kNmaxLarge; ++l) {
+      if (l + 1 <= N) {
+        const double qn = (x - tl->a[l]) * q - tl->mb[l] * qm;
+        qm = q;
+        q = qn;
+        G[l + 1] += wt * q;
+      }
+    }
+  };
+  if (lane < tl->nm) {
+    accum(Gp, u * tl->inv_p0 + s * tl->zm[lane], tl->wm[lane]);
+    accum(Gm, -u * tl->inv_p0 + s * tl->zm[lane], tl->wm[lane]);
+  }
+  const double ymax = fabs(y0);
+  if (ymax > 0.0) {
+    int li = kLadder - 1;
+    for (int j = 1; j < kLadder; ++j)
+      if (tl->lad_y[j] >= ymax) { li = j; break; }
+    const int nc = tl->lad_n[li], o = tl->lad_off[li];
+    if (lane < nc) {   // nc <= kLadderPts = 64
+      const double t = tl->ltau[o + lane], yt = y0 * t;
+      const double e = y0 * tl->llamw[o + lane] * exp(-0.5 * yt * yt);
+      accum(Gp, u * tl->inv_p0 * (1.0 - t), -e);
+      accum(Gm, -u * tl->inv_p0 * (1.0 - t), e);
+    }
+  }
+#pragma unroll
+  for (int l = 0; l <= kNmaxLarge; ++l) {
+    if (l <= N) {
+      Gp[l] = wave_sum(Gp[l]);
+      Gm[l] = wave_sum(Gm[l]);
+    }
+  }
+}
+
 // Cell phase: a 1-D grid of nwin x (kCellGroups + 1) blocks; block b maps to
 // window w and group y (with xcd_map, the groups of a window run on one
 // XCD, so the cache lines its cells share stay in one L2).  For y <
@@ -119,60 +185,7 @@ __global__ __launch_bounds__(256) void large_cell_kernel(LargeArgs A) {
     double Gp[kNmaxLarge + 1], Gm[kNmaxLarge + 1];
 #pragma unroll
     for (int l = 0; l <= kNmaxLarge; ++l) Gp[l] = Gm[l] = 0.0;
-    if (C.inv_Kn != 0.0 && tl->full) {
-      // full range (Sec. IV.A.3): G_l = E[He_l(X)], X ~ N(m u/p0, m T/p0^2),
-      // obeys G_{l+1} = ub G_l + l a G_{l-1} with a = m T/p0^2 - 1; kept as
-      // G_l / sqrt(l!) against HWs = w_k h_l(z_k) (h_l = He_l / sqrt(l!)).
-      // The mirrored half has h_l(-z) = (-1)^l h_l(z).
-      const double ub = u * tl->inv_p0, aa = T * tl->inv_p0 * tl->inv_p0 - 1.0;
-      Gp[0] = 1.0;
-      if (N >= 1) Gp[1] = ub;
-#pragma unroll
-      for (int l = 1; l < kNmaxLarge; ++l)
-        if (l + 1 <= N) Gp[l + 1] = (ub * Gp[l] + tl->sq[l] * aa * Gp[l - 1]) / tl->sq[l + 1];
-#pragma unroll
-      for (int l = 0; l <= kNmaxLarge; ++l) Gm[l] = (l & 1) ? -Gp[l] : Gp[l];
-    } else if (C.inv_Kn != 0.0) {
-      const double sT = sqrt(T), s = sT * tl->inv_p0, y0 = -u / sT;
-      auto accum = [&](double (&G)[kNmaxLarge + 1], double x, double wt) {
-        double qm = 1.0, q = x - tl->a[0];
-        G[0] += wt;
-        if (N >= 1) G[1] += wt * q;
-#pragma unroll
-        for (int l = 1; l < kNmaxLarge; ++l) {
-          if (l + 1 <= N) {
-            const double qn = (x - tl->a[l]) * q - tl->mb[l] * qm;
-            qm = q;
-            q = qn;
-            G[l + 1] += wt * q;
-          }
-        }
-      };
-      if (lane < tl->nm) {
-        accum(Gp, u * tl->inv_p0 + s * tl->zm[lane], tl->wm[lane]);
-        accum(Gm, -u * tl->inv_p0 + s * tl->zm[lane], tl->wm[lane]);
-      }
-      const double ymax = fabs(y0);
-      if (ymax > 0.0) {
-        int li = kLadder - 1;
-        for (int j = 1; j < kLadder; ++j)
-          if (tl->lad_y[j] >= ymax) { li = j; break; }
-        const int nc = tl->lad_n[li], o = tl->lad_off[li];
-        if (lane < nc) {   // nc <= kLadderPts = 64
-          const double t = tl->ltau[o + lane], yt = y0 * t;
-          const double e = y0 * tl->llamw[o + lane] * exp(-0.5 * yt * yt);
-          accum(Gp, u * tl->inv_p0 * (1.0 - t), -e);
-          accum(Gm, -u * tl->inv_p0 * (1.0 - t), e);
-        }
-      }
-#pragma unroll
-      for (int l = 0; l <= kNmaxLarge; ++l) {
-        if (l <= N) {
-          Gp[l] = wave_sum(Gp[l]);
-          Gm[l] = wave_sum(Gm[l]);
-        }
-      }
-    }
+    if (C.inv_Kn != 0.0) axis_coeffs(tl, u, T, lane, Gp, Gm);
     if (lane == 0) {
       double *out = A.cell + (int64_t)(C.cell_off + i) * kCellStride;
       out[0] = n;

@@ -26,4 +26,8 @@ void register_mixed_f16(LaunchMap &m);
 struct LargeArgs;
 void launch_large(const LargeArgs &a, int adv, int H, hipStream_t s);
 
+// The mixed-quadrature (App. A) velocity-space stage: kernels_multi.hip.
+struct MultiArgs;
+void launch_multi(const MultiArgs &a, hipStream_t s);
+
 }  // namespace hhlb

@@ -184,3 +184,34 @@ def test_precision_argument_and_mixed_workspace():
     pops = 2 * 16 * 640   # f and chi
     assert sizes[H.FP64] - sizes[H.MIXED_F32] == pytest.approx(pops * (24 - 20), abs=4096)
     assert sizes[H.MIXED_F32] == sizes[H.MIXED_BF16] == sizes[H.MIXED_F16]
+
+
+def test_multi_axes_host_checks():
+    """Mixed-quadrature sets (App. A): nodes against the oracle's product set;
+    argument and shape errors."""
+    from oracle import multi as M
+    axes = [H.Axis(H.HALF_HERMITE, 4, 3), H.Axis(H.FULL_HERMITE, 6, 5),
+            H.Axis(H.HALF_LAGUERRE, 3, 2, 0.6)]
+    p, w = H.multi_nodes(axes)
+    P, W = M.nodes([M.Axis(O.HALF, 4, 3), M.Axis(O.FULL, 6, 5), M.Axis(O.LAGUERRE, 3, 2, 0.6)])
+    np.testing.assert_allclose(p, P, rtol=4e-15, atol=0)
+    np.testing.assert_allclose(w, W, rtol=2e-13, atol=0)
+    import ctypes
+    L = H.lib()
+    nb = ctypes.c_size_t()
+    ax = H._axes(axes)
+    assert L.hhlb_multi_workspace_bytes(ax, 3, 1000, ctypes.byref(nb)) == 0
+    assert nb.value >= 2 * 1000 * 8 * 6 * 6 * 8
+    assert L.hhlb_multi_workspace_bytes(ax, 1, 10, ctypes.byref(nb)) == -1      # d = 1
+    assert L.hhlb_multi_workspace_bytes(ax, 4, 10, ctypes.byref(nb)) == -1      # d = 4
+    assert L.hhlb_multi_workspace_bytes(ax, 3, -1, ctypes.byref(nb)) == -1
+    big = H._axes([H.Axis(H.HALF_HERMITE, 8, 7), H.Axis(H.HALF_HERMITE, 8, 7), H.Axis(H.FULL_HERMITE, 4, 3)])
+    assert L.hhlb_multi_workspace_bytes(big, 3, 10, ctypes.byref(nb)) == -2     # V = 1024 > 512
+    wide = H._axes([H.Axis(H.HALF_HERMITE, 17, 16), H.Axis(H.FULL_HERMITE, 4, 3)])
+    assert L.hhlb_multi_workspace_bytes(wide, 2, 10, ctypes.byref(nb)) == -2    # V_x = 34 > 32
+    bad = H._axes([H.Axis(H.HALF_HERMITE, 4, 4), H.Axis(H.FULL_HERMITE, 4, 3)])
+    assert L.hhlb_multi_workspace_bytes(bad, 2, 10, ctypes.byref(nb)) == -1     # N >= Q
+    odd = H._axes([H.Axis(H.HALF_HERMITE, 4, 3), H.Axis(H.FULL_HERMITE, 5, 3)])
+    assert L.hhlb_multi_workspace_bytes(odd, 2, 10, ctypes.byref(nb)) == -1     # odd full-range Q
+    F = np.zeros(3)
+    assert L.hhlb_multi_step(ax, 3, None, 10, H._dptr(F), 1.0, 1e-3, 1, None, 0, None) == -1
