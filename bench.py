@@ -398,6 +398,45 @@ def run_ballistic(H, torch, np, nx=24, steps=2000, warmup=32):
             "ms_per_step": ms / steps, "steps": steps}
 
 
+def run_multi(H, torch, np, npts=1_000_000, steps=10, warmup=2):
+    """The mixed-quadrature velocity space of App. A (homogeneous gas): a
+    3-D product set HH(4) x H(4) x H(4) (V = 8 x 4 x 4 = 128, N = 3 per
+    axis), npts points started at the discrete Maxwellian w_v modulated by a
+    seeded smooth factor, F = (0.3, -0.2, 0.5), Kn = 0.1, dt = 1e-3.  HIP
+    events on the stream the steps run on.  Algorithmic HBM bytes per
+    node-update per RK-3 step: 64 (reads of y_s and y^n, writes of the next
+    stage; 8-byte values)."""
+    axes = [H.Axis(H.HALF_HERMITE, 4, 3), H.Axis(H.FULL_HERMITE, 4, 3), H.Axis(H.FULL_HERMITE, 4, 3)]
+    p, w = H.multi_nodes(axes)
+    V = w.size
+    rng = np.random.default_rng(0)
+    mod = 1.0 + 0.05 * np.sin(rng.random((npts, 1)) * 2 * np.pi + np.arange(V)[None, :] * 0.1)
+    f = torch.from_numpy(w[None, :] * mod).cuda()
+    del mod
+    s = H.MultiSolver(axes, npts, [0.3, -0.2, 0.5], 0.1)
+    s.step(f, 1e-3, warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.step(f, 1e-3, steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    assert bool(torch.isfinite(f).all()), "multi: non-finite populations"
+    nu = npts * V
+    gbs = 64.0 * nu / (ms / 1e3) / 1e9
+    out = {"workload": f"App. A mixed quadrature, homogeneous gas: HH(4) x H(4) x H(4) (V = {V}, N = 3 per "
+                       f"axis), {npts} points, F = (0.3, -0.2, 0.5), Kn = 0.1, dt = 1e-3, FP64",
+           "value": nu / (ms / 1e3), "unit": "node-updates/s", "ms_per_step": ms, "steps": steps,
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "hhlb::multi_kernel (one RK-3 stage)",
+                        "algorithmic_bytes_per_node_update_per_step": 64}}
+    del f
+    torch.cuda.empty_cache()
+    return out
+
+
 def moment_diff(np, a, b):
     """err_n = max|dn|/max n, err_u = max|du|/sqrt(T_left), err_T = max|dT|/max T."""
     n0, u0, T0 = a
@@ -429,6 +468,10 @@ def main():
     ap.add_argument("--max-steps", type=int, default=3_000_000)
     ap.add_argument("--no-ballistic", action="store_true",
                     help="skip the HHLB(20;200) ballistic record (the node-parallel path)")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the mixed-quadrature (App. A) record")
+    ap.add_argument("--multi-only", action="store_true",
+                    help="only run the mixed-quadrature (App. A) record")
     ap.add_argument("--ballistic-only", action="store_true",
                     help="only run the HHLB(20;200) ballistic record")
     ap.add_argument("--ballistic-nx", type=int, default=24,
@@ -451,6 +494,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": n * 8, "copies": 3}))
+        return
+    if args.multi_only:
+        import numpy as np
+        import torch
+        import paper_1708_03249_amd as H
+        print(json.dumps({"multi_d": run_multi(H, torch, np)}), flush=True)
         return
     if args.ballistic_only:
         import numpy as np
@@ -531,6 +580,9 @@ def main():
         print("[bench] ballistic HHLB(20;200): 8 channels x Nx=24", file=sys.stderr, flush=True)
         out["ballistic_q200"] = run_ballistic(H, torch, np, nx=args.ballistic_nx,
                                               steps=args.ballistic_steps)
+    if not args.no_multi:
+        print("[bench] mixed quadrature (App. A): 1e6 points x V=128", file=sys.stderr, flush=True)
+        out["multi_d"] = run_multi(H, torch, np)
     if args.batch_channels > 0:
         out["batched"] = run_batch(H, torch, np, args)
     if not args.no_cpu_baseline:
