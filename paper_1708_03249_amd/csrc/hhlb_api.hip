@@ -1546,7 +1546,7 @@ hhlb_status hhlb_multi_rhs(const hhlb_axis *axes, int32_t d, const double *f_dev
   a.in = f_dev;
   a.out = L_dev;
   a.rhs_only = 1;
-  hhlb::launch_multi(a, s);
+  hhlb::launch_multi(a, s, ms->V);
   HIP_TRY(hipGetLastError());
   return HHLB_OK;
 }
@@ -1570,11 +1570,11 @@ hhlb_status hhlb_multi_step(const hhlb_axis *axes, int32_t d, double *f_dev, int
     // Eq. (rk3): y1 = y + dt L[y]; y2 = 3/4 y + 1/4 (y1 + dt L[y1]);
     // y+ = 1/3 y + 2/3 (y2 + dt L[y2])
     a.in = f_dev; a.base = nullptr; a.out = y1; a.a_base = 0.0; a.b_stage = 1.0;
-    hhlb::launch_multi(a, s);
+    hhlb::launch_multi(a, s, ms->V);
     a.in = y1; a.base = f_dev; a.out = y2; a.a_base = 0.75; a.b_stage = 0.25;
-    hhlb::launch_multi(a, s);
+    hhlb::launch_multi(a, s, ms->V);
     a.in = y2; a.base = f_dev; a.out = f_dev; a.a_base = 1.0 / 3.0; a.b_stage = 2.0 / 3.0;
-    hhlb::launch_multi(a, s);
+    hhlb::launch_multi(a, s, ms->V);
   }
   HIP_TRY(hipGetLastError());
   return HHLB_OK;

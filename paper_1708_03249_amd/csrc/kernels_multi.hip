@@ -3,13 +3,20 @@
 
 namespace hhlb {
 
+// W lanes per point: W = 64 (one point per wave, V <= 512) or W = 16 (four
+// points per wave, V <= 128); each lane holds velocities sub + W t, t < 8.
+template <int W>
 __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
-  __shared__ double s_f[kMultiWaves][kMultiVmax];
-  __shared__ double s_g[kMultiWaves][kMultiAxes * kMultiVaxis];
+  constexpr int P = 64 / W;                 // points per wave
+  constexpr int VW = 8 * W;                 // largest V for this width
+  constexpr int KT = VW / W;
+  __shared__ double s_f[kMultiWaves][P * VW];
+  __shared__ double s_g[kMultiWaves][P * kMultiAxes * kMultiVaxis];
   __shared__ double s_K[kMultiAxes * kMultiVaxis * kMultiVaxis];   // the axes' K_a, row-major
   __shared__ double s_p[kMultiAxes * kMultiVaxis];
   __shared__ int32_t s_idx[kMultiVmax];   // packed per-axis indices of each velocity
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int seg = lane / W, sub = lane % W;
   const DevMulti *tm = A.tm;
   const int d = tm->d, V = tm->V;
   // the block stages the axes' tables (every wave takes this barrier)
@@ -26,16 +33,17 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
     for (int t = threadIdx.x; t < V; t += 64 * kMultiWaves) s_idx[t] = gi[t];
   }
   __syncthreads();
-  const int64_t pt = (int64_t)blockIdx.x * kMultiWaves + wave;
-  if (pt >= A.npts) return;   // wave-uniform; only wave-level barriers follow
+  // a point past the end computes on the last point's data and stores nothing
+  const int64_t pt0 = ((int64_t)blockIdx.x * kMultiWaves + wave) * P + seg;
+  const bool valid = pt0 < A.npts;
+  const int64_t pt = valid ? pt0 : A.npts - 1;
   const double *y = A.in + pt * V;
-  double *sf = s_f[wave], *sg = s_g[wave];
-  constexpr int KT = kMultiVmax / 64;
+  double *sf = s_f[wave] + seg * VW, *sg = s_g[wave] + seg * kMultiAxes * kMultiVaxis;
   // per-axis indices of this lane's velocities (v = (i V_y + j) V_z + k)
   int ia[KT][kMultiAxes];
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
-    const int v = lane + 64 * t, w = v < V ? s_idx[v] : 0;
+    const int v = sub + W * t, w = v < V ? s_idx[v] : 0;
 #pragma unroll
     for (int a = 0; a < kMultiAxes; ++a) ia[t][a] = (w >> (8 * a)) & 0xff;
   }
@@ -44,14 +52,14 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   double fv[KT];
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
-    const int v = lane + 64 * t;
+    const int v = sub + W * t;
     fv[t] = v < V ? y[v] : 0.0;
     if (v < V) sf[v] = fv[t];
   }
   double n = 0.0, mom[kMultiAxes] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
-    const int v = lane + 64 * t;
+    const int v = sub + W * t;
     if (v < V) {
       n += fv[t];
 #pragma unroll
@@ -59,15 +67,15 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
         if (a < d) mom[a] += s_p[a * kMultiVaxis + ia[t][a]] * fv[t];
     }
   }
-  n = wave_sum(n);
+  n = seg_sum<W>(n);
   double u[kMultiAxes] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int a = 0; a < kMultiAxes; ++a)
-    if (a < d) u[a] = wave_sum(mom[a]) / n;
+    if (a < d) u[a] = seg_sum<W>(mom[a]) / n;
   double c2 = 0.0;
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
-    const int v = lane + 64 * t;
+    const int v = sub + W * t;
     if (v < V) {
       double q = 0.0;
 #pragma unroll
@@ -79,7 +87,7 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
       c2 += q * fv[t];
     }
   }
-  const double T = wave_sum(c2) / (d * n);
+  const double T = seg_sum<W>(c2) / (d * n);
 
   // per-axis 1-D equilibrium factors g_a[i] (App. A.2) into LDS; a runtime
   // loop over the axes keeps one inlined copy of axis_coeffs (code size)
@@ -88,10 +96,10 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
     for (int a = 0; a < d; ++a) {
       const double ua = a == 0 ? u[0] : (a == 1 ? u[1] : u[2]);
       double Gp[kNmaxLarge + 1], Gm[kNmaxLarge + 1];
-      axis_coeffs(&tm->ax[a], ua, T, lane, Gp, Gm);
+      axis_coeffs<W>(&tm->ax[a], ua, T, sub, Gp, Gm);
       const int Va = tm->Va[a], H = Va / 2, N = tm->ax[a].N;
-      if (lane < Va) {
-        const int k = lane < H ? lane : lane - H;
+      for (int i = sub; i < Va; i += W) {
+        const int k = i < H ? i : i - H;
         const double *hw = A.tab + tm->hw_off[a] + k * (N + 1);
         double gp = 0.0, gm = 0.0;
 #pragma unroll
@@ -100,7 +108,7 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
             gp = fma(hw[l], Gp[l], gp);
             gm = fma(hw[l], Gm[l], gm);
           }
-        sg[a * kMultiVaxis + lane] = lane < H ? gp : gm;
+        sg[a * kMultiVaxis + i] = i < H ? gp : gm;
       }
     }
   }
@@ -109,7 +117,7 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   // force contractions, BGK and the RK-3 combination (runtime loops: the
   // populations come back from LDS)
   const double F0 = A.F[0], F1 = A.F[1], F2 = A.F[2];
-  for (int v = lane; v < V; v += 64) {
+  for (int v = sub; v < V; v += W) {
     const double fvv = sf[v];
     const int w = s_idx[v];
     double force = 0.0, g = n;
@@ -125,14 +133,20 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
     double L = -force;
     if (A.inv_Kn != 0.0) L -= (fvv - g) * (n * A.inv_Kn);
     const int64_t o = pt * V + v;
-    A.out[o] = A.rhs_only ? L : A.a_base * (A.a_base != 0.0 ? A.base[o] : 0.0) + A.b_stage * (fvv + A.dt * L);
+    if (valid)
+      A.out[o] = A.rhs_only ? L : A.a_base * (A.a_base != 0.0 ? A.base[o] : 0.0) + A.b_stage * (fvv + A.dt * L);
   }
 }
 
-void launch_multi(const MultiArgs &a, hipStream_t s) {
+void launch_multi(const MultiArgs &a, hipStream_t s, int V) {
   if (a.npts <= 0) return;
-  const int64_t blocks = (a.npts + kMultiWaves - 1) / kMultiWaves;
-  hipLaunchKernelGGL(multi_kernel, dim3((unsigned)blocks), dim3(64 * kMultiWaves), 0, s, a);
+  if (V <= 8 * 16) {   // four points per wave
+    const int64_t blocks = (a.npts + 4 * kMultiWaves - 1) / (4 * kMultiWaves);
+    hipLaunchKernelGGL(multi_kernel<16>, dim3((unsigned)blocks), dim3(64 * kMultiWaves), 0, s, a);
+  } else {
+    const int64_t blocks = (a.npts + kMultiWaves - 1) / kMultiWaves;
+    hipLaunchKernelGGL(multi_kernel<64>, dim3((unsigned)blocks), dim3(64 * kMultiWaves), 0, s, a);
+  }
 }
 
 }  // namespace hhlb

@@ -57,11 +57,22 @@ struct LargeArgs {
   int32_t xcd_map;                // 1: the blocks of a window run on one XCD
 };
 
-// Equilibrium coefficients of one axis at (u, T) for a whole wave (every
-// lane returns the same G^+_l and G^-_l, l <= N): Sec. IV.B.3 by the change
-// of variables, the main rule and the correction spread over the lanes and
-// collected by wave sums; for the full range the closed-form recurrence of
-// Sec. IV.A.3.  Called by every lane of the wave.
+// Sum over aligned segments of W lanes (W = 64: the whole wave).
+template <int W>
+__device__ __forceinline__ double seg_sum(double x) {
+#pragma unroll
+  for (int off = W / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Equilibrium coefficients of one axis at (u, T) for a segment of W lanes
+// (every lane of the segment returns the same G^+_l and G^-_l, l <= N;
+// lane = the lane's index within its segment): Sec. IV.B.3 by the change of
+// variables, the main rule and the correction spread over the lanes and
+// collected by segment sums; for the full range the closed-form recurrence
+// of Sec. IV.A.3.  Called by every lane of the wave; W >= 16 holds the main
+// rule (at most 11 points for N <= 20) and the largest correction (16).
+template <int W = 64>
 __device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double T, int lane,
                                             double (&Gp)[kNmaxLarge + 1], double (&Gm)[kNmaxLarge + 1]) {
   const int N = tl->N;
@@ -107,7 +118,7 @@ __device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double
     for (int j = 1; j < kLadder; ++j)
       if (tl->lad_y[j] >= ymax) { li = j; break; }
     const int nc = tl->lad_n[li], o = tl->lad_off[li];
-    if (lane < nc) {   // nc <= kLadderPts = 64
+    if (lane < nc) {   // nc <= 16 (the largest count of the ladder)
       const double t = tl->ltau[o + lane], yt = y0 * t;
       const double e = y0 * tl->llamw[o + lane] * exp(-0.5 * yt * yt);
       accum(Gp, u * tl->inv_p0 * (1.0 - t), -e);
@@ -117,8 +128,8 @@ __device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double
 #pragma unroll
   for (int l = 0; l <= kNmaxLarge; ++l) {
     if (l <= N) {
-      Gp[l] = wave_sum(Gp[l]);
-      Gm[l] = wave_sum(Gm[l]);
+      Gp[l] = seg_sum<W>(Gp[l]);
+      Gm[l] = seg_sum<W>(Gm[l]);
     }
   }
 }

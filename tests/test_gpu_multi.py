@@ -30,7 +30,9 @@ SETS = [
     ("HH(3)xHH(3)xH(4)", [(0, 3, 2, 1.0), (0, 3, 2, 1.0), (1, 4, 3, 1.0)], [0.5, -0.25, 0.8]),
     ("H(6)xHH(4,p0=1.2)xL(3,p0=0.6)", [(1, 6, 5, 1.0), (0, 4, 3, 1.2), (2, 3, 2, 0.6)], [-0.4, 0.9, 0.3]),
     ("HH(8)xH(8)xH(4), V = 512", [(0, 8, 7, 1.0), (1, 8, 7, 1.0), (1, 4, 3, 1.0)], [0.2, 0.1, -0.6]),
+    ("HH(2)xL(3,p0=0.6)xH(4), V = 96", [(0, 2, 1, 1.0), (2, 3, 2, 0.6), (1, 4, 3, 1.0)], [0.4, -0.7, 0.2]),
 ]
+# sets with V <= 128 run four points per wave (16 lanes each), larger ones one
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -77,7 +79,7 @@ def test_multi_rhs_against_oracle(name, spec, F, Kn):
     assert err < TOL, err
 
 
-@pytest.mark.parametrize("name,spec,F", SETS[:3], ids=[s[0] for s in SETS[:3]])
+@pytest.mark.parametrize("name,spec,F", SETS[:3] + SETS[4:], ids=[s[0] for s in SETS[:3] + SETS[4:]])
 def test_multi_step_against_oracle(name, spec, F):
     import torch
     import paper_1708_03249_amd as H
