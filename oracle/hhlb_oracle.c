@@ -212,12 +212,18 @@ static void gl_nodes(int n, qf *x, qf *w) {
 
 /* Recurrence coefficients of omega(z) = exp(-z^2/2)/sqrt(2 pi) on [0, inf)
  * by the discretised Stieltjes procedure (orthonormal form): the measure is
- * replaced by a composite 40-point Gauss-Legendre rule on 110 panels of
- * width 0.4 over [0, 44] (omega(44) = 1e-421, far below what the rules
- * resolve).  Returns a_0..a_{n-1}, b_0..b_n (b_0 = int omega). */
+ * replaced by a composite 40-point Gauss-Legendre rule on 500 panels of
+ * width 0.1 over [0, 50] (omega(50) = 1e-543, far below what the rules
+ * resolve).  The panel width follows from the oscillation of h_l: a
+ * half-range polynomial of degree l oscillates like a full-range one of
+ * degree 2l, so near z = 0 the integrand h_l^2 has half-wavelength about
+ * pi / (4 sqrt(l)), 0.05 at l = 256; 40 points on 0.1 integrate it to
+ * float128 rounding for every l <= 258 (panels of 0.4 lost digits above
+ * l = 150, reaching 1e-6 at l = 256).  Returns a_0..a_{n-1}, b_0..b_n
+ * (b_0 = int omega). */
 static int hh_stieltjes(int n, qf *a, qf *b) {
-  enum { PAN = 110, PER = 40 };
-  const qf width = 0.4Q;
+  enum { PAN = 500, PER = 40 };
+  const qf width = 0.1Q;
   qf gx[PER], gw[PER];
   gl_nodes(PER, gx, gw);
   const int M = PAN * PER;

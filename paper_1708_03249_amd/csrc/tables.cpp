@@ -62,8 +62,12 @@ int sturm_count(const Rule &r, int n, ld x) {
 // [0, inf): returns a[0..n-1], b[0..n] of the monic recurrence
 // pi_{l+1} = (z - a_l) pi_l - b_l pi_{l-1}, b_0 = int omega.
 void stieltjes_half(int n, std::vector<ld> &a, std::vector<ld> &b) {
-  const int panels = 80, per = 48;
-  const ld width = 0.5L;
+  // 48-point Gauss-Legendre panels of width 1/8 on [0, 50]: near z = 0 the
+  // squared degree-l family oscillates with half-wavelength about
+  // pi / (4 sqrt(l)) (0.05 at l = 258), which these panels resolve to long
+  // double rounding; wider panels lose digits above degree 150
+  const int panels = 400, per = 48;
+  const ld width = 0.125L;
   std::vector<ld> gx(per), gw(per);
   {
     std::vector<ld> tau, lam;

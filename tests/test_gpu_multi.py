@@ -134,3 +134,29 @@ def test_multi_drift_invariants_at_scale():
     ref = M.run(oaxes, f[j:j + 1], F, Kn, dt, nsteps)
     got = fd[j:j + 1].cpu().numpy()
     assert np.max(np.abs(got - ref)) < TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("spec", [[(0, 4, 3, 1.0), (1, 4, 3, 1.0)],
+                                  [(0, 8, 7, 1.0), (1, 8, 7, 1.0), (1, 4, 3, 1.0)]],
+                         ids=["V = 32, four points per wave", "V = 512, one point per wave"])
+def test_multi_single_point_and_empty(spec):
+    """npts = 1 (a wave with one valid point) against the oracle, and
+    npts = 0 (nothing launched, the state untouched)."""
+    import torch
+    import paper_1708_03249_amd as H
+    haxes, oaxes = _axes(spec)
+    F = np.array([0.3, -0.5, 0.2])[:len(spec)]
+    f = _state(oaxes, 1, 21)
+    ref = M.rhs(oaxes, f, F, 0.4)
+    s = H.MultiSolver(haxes, 1, F, 0.4)
+    fd = torch.from_numpy(f).cuda()
+    Ld = torch.full_like(fd, float("nan"))
+    s.rhs(fd, Ld)
+    torch.cuda.synchronize()
+    scale = np.abs(ref).max() + np.abs(f).max() * f.sum() / 0.4
+    assert np.max(np.abs(Ld.cpu().numpy() - ref)) < TOL * scale
+    s0 = H.MultiSolver(haxes, 0, F, 0.4)
+    empty = torch.empty((0, f.shape[1]), dtype=torch.float64, device="cuda")
+    s0.step(empty, 1e-3, 3)
+    s0.rhs(empty, empty)
+    torch.cuda.synchronize()

@@ -165,6 +165,19 @@ def test_full_range_hlb_20_500_ballistic_setup():
     _check([ch], 30, what="HLB(20;500)")
 
 
+def test_large_q_limits_minimum_grid():
+    """The node-parallel path at its limits on the smallest grid (Nx = 8,
+    both walls in one window): half-range Q = 256 (one chunk of 16 MFMA
+    steps per wave, 16 tiles per half) with chi and BGK, and full-range
+    Q = 512 (two chunks, the dense contraction over 512 rows) with BGK."""
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=256, N=20, Nx=8, adv=h.WENO5, transverse_dof=2,
+                       stretch_A=0.5, Kn=0.3, g=-0.4, T_left=1.2, T_right=0.9, dt=-0.5),
+             h.Channel(quad=h.FULL_HERMITE, Q=512, N=20, Nx=8, adv=h.UPWIND3, transverse_dof=0,
+                       Kn=0.5, g=0.3, T_left=0.9, T_right=1.1, dt=-0.5)]
+    _check(chans, 5, what="large Q limits, Nx = 8")
+
+
 def test_ballistic_hhlb_20_200_setup():
     """The paper's ballistic configuration (Sec. VI.D): HHLB(20;200), V = 400,
     Nx = 24, A = 0.99, Kn = inf, g = 0.1, T_left = 1.4, T_right = 0.6,

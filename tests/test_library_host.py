@@ -57,6 +57,23 @@ def test_host_equilibrium_laguerre_matches_oracle(Q, N, p0, u, T):
     np.testing.assert_allclose(g, go, rtol=0, atol=2e-15 * np.abs(go).max())
 
 
+@pytest.mark.parametrize("Q", [40, 200, 256])
+def test_host_half_range_large_q_tables_match_oracle(Q):
+    """Half-range HHLB(20;Q) tables of the node-parallel path against the
+    oracle (two independent discretised Stieltjes procedures, long double
+    and float128), columns of K compared relative to their largest entry."""
+    p, w = H.nodes(H.HALF_HERMITE, Q)
+    K = H.force_matrix(H.HALF_HERMITE, Q)
+    po, wo, Ko, *_ = O.tables(O.HALF, Q)
+    np.testing.assert_allclose(p, po, rtol=2e-15, atol=0)
+    live = wo > 1e-280
+    np.testing.assert_allclose(w[live], wo[live], rtol=1e-13, atol=0)
+    assert np.max(np.abs(K - Ko) / np.abs(Ko).max(axis=0)) < 1e-13
+    g = H.equilibrium(H.HALF_HERMITE, Q, 20, 1.0, 0.1, 1.2)
+    go = O.equilibrium(O.HALF, Q, 20, 1.0, 0.1, 1.2)
+    np.testing.assert_allclose(g, go, rtol=0, atol=2e-15 * np.abs(go).max())
+
+
 @pytest.mark.parametrize("Q", [40, 100, 200])
 def test_host_full_range_large_q_tables_match_oracle(Q):
     """Full-range HLB(20;Q) tables of the node-parallel path against the

@@ -46,7 +46,7 @@ def test_recurrence_construction_matches_monomial_one(Q, recurrence_everywhere):
     np.testing.assert_allclose(g, gm, rtol=0, atol=2e-15 * np.abs(gm).max())
 
 
-@pytest.mark.parametrize("Q", [17, 40, 100, 200])
+@pytest.mark.parametrize("Q", [17, 40, 100, 200, 256])
 def test_large_q_quadrature_exact_to_degree_2Q_minus_1(Q):
     """Sec. IV.B.1: exactness for z^s, s <= 2Q-1 (every s up to 40, then
     every 7th, and 2Q-1), to the rounding of the FP64 table (node rounding
@@ -75,6 +75,48 @@ def _moment_identity_error(p, K, s, cols):
         scale = mp.fsum(abs(t) for t in terms) + abs(rhs)
         worst = max(worst, abs(lhs - rhs) / scale)
     return float(worst)
+
+
+def _gauss_recurrence(n):
+    """Monic recurrence pi_{k+1} = (z - alpha_k) pi_k - beta_k pi_{k-1} of the
+    half-range weight, from its exact moments mu_s (Gamma function) by the
+    classical Chebyshev algorithm in mp.dps digits.  The algorithm is
+    ill-conditioned: at n = 257 it needs about 330 digits."""
+    mu = [mu_half(s) for s in range(2 * n)]
+    alpha, beta = [mp.mpf(0)] * n, [mp.mpf(0)] * n
+    sig_m, sig = [mp.mpf(0)] * (2 * n), list(mu)
+    alpha[0], beta[0] = mu[1] / mu[0], mu[0]
+    for k in range(1, n):
+        new = [mp.mpf(0)] * (2 * n)
+        for l in range(k, 2 * n - k):
+            new[l] = sig[l + 1] - alpha[k - 1] * sig[l] - beta[k - 1] * sig_m[l]
+        alpha[k] = new[k + 1] / new[k] - sig[k] / sig[k - 1]
+        beta[k] = new[k] / sig[k - 1]
+        sig_m, sig = sig, new
+    return alpha, beta
+
+
+def test_large_q_nodes_are_gauss_roots():
+    """Sec. IV.B.1 at Q = 256, the largest half-range order: every node is a
+    root of the degree-Q orthogonal polynomial of the half-range weight, that
+    polynomial taken from the exact moments (not from the oracle's own
+    discretised Stieltjes procedure): the Newton step pi_Q / pi_Q' at each
+    node is below 1e-15 of the node.  (Moment exactness cannot decide this:
+    at Q = 256 node sets 1e-9 apart reproduce every moment to 1e-14.)"""
+    Q = 256
+    mp.mp.dps = 400
+    alpha, beta = _gauss_recurrence(Q + 1)
+    p, *_ = O.tables(O.HALF, Q)
+    worst = 0.0
+    for z in p[:Q]:
+        z = mp.mpf(z)
+        pm, pc, dm, dc = mp.mpf(0), mp.mpf(1), mp.mpf(0), mp.mpf(0)
+        for k in range(Q):
+            pn = (z - alpha[k]) * pc - (beta[k] * pm if k > 0 else 0)
+            dn = pc + (z - alpha[k]) * dc - (beta[k] * dm if k > 0 else 0)
+            pm, pc, dm, dc = pc, pn, dc, dn
+        worst = max(worst, float(abs(pc / dc / z)))
+    assert worst < 1e-15, worst
 
 
 @pytest.mark.parametrize("Q", [40, 200])
