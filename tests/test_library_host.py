@@ -149,8 +149,9 @@ def test_create_unsupported_shape_and_null_calls():
     assert st == -1                              # odd full-range Q
     st, _ = _create([H.Channel(Q=24)], precision=H.MIXED_F32)
     assert st == -2
-    for ch in (H.Channel(Q=24), H.Channel(quad=H.FULL_HERMITE, Q=20), H.Channel(Q=256),
-               H.Channel(quad=H.FULL_HERMITE, Q=512)):
+    # (the largest shapes, half-range Q = 256 and full-range Q = 512, are
+    # created by the GPU tests and their tables checked above)
+    for ch in (H.Channel(Q=24), H.Channel(quad=H.FULL_HERMITE, Q=20)):
         st, h = _create([ch])
         assert st == 0 and H.lib().hhlb_destroy(h) == 0
     L = H.lib()

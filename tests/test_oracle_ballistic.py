@@ -28,7 +28,7 @@ def test_density_and_temperature_are_moments_of_f_bal(gp, Tp, Tm):
     """Eqs. (bal_n), (bal_temp) against Eq. (fmoms) applied to Eq. (f_bal):
     n = int f dp, n T = int p^2/m f dp (u = 0), and the mass flux vanishes."""
     mp.mp.dps = 40
-    for x in XS:
+    for x in XS[::2]:      # both walls' neighbourhoods and the middle
         n = _pmoments(x, gp, Tp, Tm, 0)
         j = _pmoments(x, gp, Tp, Tm, 1)
         e2 = _pmoments(x, gp, Tp, Tm, 2)
