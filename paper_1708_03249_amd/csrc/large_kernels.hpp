@@ -1,19 +1,22 @@
 // Node-parallel FP64 stage for large velocity sets, equilibrium order
 // N <= 20: the half-range model with 17 <= Q <= 256 nodes per half and the
 // full-range model with 18 <= Q <= 512 nodes, the paper's HHLB(20;Q) and
-// HLB(20;Q) models of the ballistic study (Sec. VI.D).  A lane holds one
-// cell, as in stage_kernel_half, but the Q nodes of a half no longer fit a
-// lane's registers, so one stage runs as two kernels:
+// HLB(20;Q) models of the ballistic study (Sec. VI.D).  The nodes of a half
+// no longer fit a lane's registers, so one stage runs as two kernels:
 //   large_cell_kernel: one wave per cell, lanes over nodes and then over
 //     quadrature points: the moments (Eq. fmoms), 1/tau, the rank-1 force
-//     projections and the half-range equilibrium coefficients of both halves
-//     (Sec. IV.B.3, the change of variables of stage_kernel_half); per
-//     channel, the wall densities (Eq. nplus_def).
+//     projections and the equilibrium coefficients of both halves (half
+//     range: Sec. IV.B.3 by the change of variables of stage_kernel_half;
+//     full range: the closed form of Sec. IV.A.3); per channel, the wall
+//     densities (Eq. nplus_def).
 //   large_node_kernel: per window and tile of 16 nodes of one half, the
-//     force -F (K y)_k with the within-half block (Eq. hh_Kk_hh) contracted
-//     on FP64 MFMA tiles, the wall ghosts (Sec. IV.C.3), BGK towards the
-//     synthesised equilibrium, WENO-5 / upwind-3 advection (the lane-parallel
-//     face values of stage_kernel_half) and the RK-3 combination.
+//     force -F (K y)_k contracted on FP64 MFMA tiles (half range: the
+//     within-half block of Eq. hh_Kk_hh plus the rank-1 cross term; full
+//     range: the dense matrix of Eq. H_Kk), the wall ghosts (Sec. IV.C.3),
+//     BGK towards the synthesised equilibrium, WENO-5 / upwind-3 advection
+//     (the lane-parallel face values of stage_kernel_half) and the RK-3
+//     combination.  The lanes of the node phase hold cells, as in
+//     stage_kernel_half.
 #pragma once
 #include "step_kernels.hpp"
 
