@@ -12,7 +12,7 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   constexpr int KT = VW / W;
   __shared__ double s_f[kMultiWaves][P * VW];
   __shared__ double s_g[kMultiWaves][P * kMultiAxes * kMultiVaxis];
-  __shared__ double s_K[kMultiAxes * kMultiVaxis * kMultiVaxis];   // the axes' K_a, row-major
+  extern __shared__ double s_K[];   // the axes' K_a, row-major, back to back (sum V_a^2 doubles)
   __shared__ double s_p[kMultiAxes * kMultiVaxis];
   __shared__ int32_t s_idx[kMultiVmax];   // packed per-axis indices of each velocity
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -20,12 +20,13 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   const DevMulti *tm = A.tm;
   const int d = tm->d, V = tm->V;
   // the block stages the axes' tables (every wave takes this barrier)
+  int ko[kMultiAxes] = {0, 0, 0};   // offset of K_a in s_K
 #pragma unroll
   for (int a = 0; a < kMultiAxes; ++a) {
     if (a >= d) break;
     const int Va = tm->Va[a];
-    for (int t = threadIdx.x; t < Va * Va; t += 64 * kMultiWaves)
-      s_K[a * kMultiVaxis * kMultiVaxis + t] = A.tab[tm->k_off[a] + t];
+    if (a + 1 < kMultiAxes) ko[a + 1] = ko[a] + Va * Va;
+    for (int t = threadIdx.x; t < Va * Va; t += 64 * kMultiWaves) s_K[ko[a] + t] = A.tab[tm->k_off[a] + t];
     if ((int)threadIdx.x < Va) s_p[a * kMultiVaxis + threadIdx.x] = A.tab[tm->p_off[a] + threadIdx.x];
   }
   {
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
     for (int a = 0; a < d; ++a) {
       const int st = tm->stride[a], Va = tm->Va[a];
       const int i = (w >> (8 * a)) & 0xff, v0 = v - i * st;
-      const double *K = s_K + a * kMultiVaxis * kMultiVaxis + i * Va;
+      const double *K = s_K + (a == 0 ? ko[0] : (a == 1 ? ko[1] : ko[2])) + i * Va;
       double acc = 0.0;
       for (int ip = 0; ip < Va; ++ip) acc = fma(K[ip], sf[v0 + ip * st], acc);
       force = fma(a == 0 ? F0 : (a == 1 ? F1 : F2), acc, force);
@@ -138,14 +139,15 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   }
 }
 
-void launch_multi(const MultiArgs &a, hipStream_t s, int V) {
+void launch_multi(const MultiArgs &a, hipStream_t s, int V, int k_doubles) {
   if (a.npts <= 0) return;
+  const size_t shm = sizeof(double) * (size_t)k_doubles;   // the K_a tables
   if (V <= 8 * 16) {   // four points per wave
     const int64_t blocks = (a.npts + 4 * kMultiWaves - 1) / (4 * kMultiWaves);
-    hipLaunchKernelGGL(multi_kernel<16>, dim3((unsigned)blocks), dim3(64 * kMultiWaves), 0, s, a);
+    hipLaunchKernelGGL(multi_kernel<16>, dim3((unsigned)blocks), dim3(64 * kMultiWaves), shm, s, a);
   } else {
     const int64_t blocks = (a.npts + kMultiWaves - 1) / kMultiWaves;
-    hipLaunchKernelGGL(multi_kernel<64>, dim3((unsigned)blocks), dim3(64 * kMultiWaves), 0, s, a);
+    hipLaunchKernelGGL(multi_kernel<64>, dim3((unsigned)blocks), dim3(64 * kMultiWaves), shm, s, a);
   }
 }
 
