@@ -1381,6 +1381,7 @@ struct MultiSet {
   std::vector<char> blob;
   int d = 0, V = 0;
   int kdoubles = 0;   // sum of V_a^2: the K_a tables the kernel stages in LDS
+  int nmax = 0;       // the largest equilibrium order of the axes
 };
 
 std::mutex g_multi_mu;
@@ -1460,7 +1461,10 @@ hhlb_status multi_set(const hhlb_axis *axes, int32_t d, std::shared_ptr<const Mu
     std::memcpy(ms->blob.data() + sizeof hdr + sizeof(double) * tail.size(), idx.data(), sizeof(int32_t) * V);
     ms->d = d;
     ms->V = V;
-    for (int a = 0; a < d; ++a) ms->kdoubles += hdr.Va[a] * hdr.Va[a];
+    for (int a = 0; a < d; ++a) {
+      ms->kdoubles += hdr.Va[a] * hdr.Va[a];
+      ms->nmax = std::max(ms->nmax, (int)axes[a].N);
+    }
     std::lock_guard<std::mutex> lk(g_multi_mu);
     out = g_multi_cache.emplace(key, ms).first->second;
   } catch (...) {
@@ -1548,7 +1552,7 @@ hhlb_status hhlb_multi_rhs(const hhlb_axis *axes, int32_t d, const double *f_dev
   a.in = f_dev;
   a.out = L_dev;
   a.rhs_only = 1;
-  hhlb::launch_multi(a, s, ms->V, ms->kdoubles);
+  hhlb::launch_multi(a, s, ms->V, ms->kdoubles, ms->nmax);
   HIP_TRY(hipGetLastError());
   return HHLB_OK;
 }
@@ -1572,11 +1576,11 @@ hhlb_status hhlb_multi_step(const hhlb_axis *axes, int32_t d, double *f_dev, int
     // Eq. (rk3): y1 = y + dt L[y]; y2 = 3/4 y + 1/4 (y1 + dt L[y1]);
     // y+ = 1/3 y + 2/3 (y2 + dt L[y2])
     a.in = f_dev; a.base = nullptr; a.out = y1; a.a_base = 0.0; a.b_stage = 1.0;
-    hhlb::launch_multi(a, s, ms->V, ms->kdoubles);
+    hhlb::launch_multi(a, s, ms->V, ms->kdoubles, ms->nmax);
     a.in = y1; a.base = f_dev; a.out = y2; a.a_base = 0.75; a.b_stage = 0.25;
-    hhlb::launch_multi(a, s, ms->V, ms->kdoubles);
+    hhlb::launch_multi(a, s, ms->V, ms->kdoubles, ms->nmax);
     a.in = y2; a.base = f_dev; a.out = f_dev; a.a_base = 1.0 / 3.0; a.b_stage = 2.0 / 3.0;
-    hhlb::launch_multi(a, s, ms->V, ms->kdoubles);
+    hhlb::launch_multi(a, s, ms->V, ms->kdoubles, ms->nmax);
   }
   HIP_TRY(hipGetLastError());
   return HHLB_OK;

@@ -5,7 +5,9 @@ namespace hhlb {
 
 // W lanes per point: W = 64 (one point per wave, V <= 512) or W = 16 (four
 // points per wave, V <= 128); each lane holds velocities sub + W t, t < 8.
-template <int W>
+// NM bounds the axes' equilibrium orders (7 or 20: the size of the register
+// arrays of the coefficients).
+template <int W, int NM>
 __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   constexpr int P = 64 / W;                 // points per wave
   constexpr int VW = 8 * W;                 // largest V for this width
@@ -96,15 +98,15 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
 #pragma unroll 1
     for (int a = 0; a < d; ++a) {
       const double ua = a == 0 ? u[0] : (a == 1 ? u[1] : u[2]);
-      double Gp[kNmaxLarge + 1], Gm[kNmaxLarge + 1];
-      axis_coeffs<W>(&tm->ax[a], ua, T, sub, Gp, Gm);
+      double Gp[NM + 1], Gm[NM + 1];
+      axis_coeffs<W, NM>(&tm->ax[a], ua, T, sub, Gp, Gm);
       const int Va = tm->Va[a], H = Va / 2, N = tm->ax[a].N;
       for (int i = sub; i < Va; i += W) {
         const int k = i < H ? i : i - H;
         const double *hw = A.tab + tm->hw_off[a] + k * (N + 1);
         double gp = 0.0, gm = 0.0;
 #pragma unroll
-        for (int l = 0; l <= kNmaxLarge; ++l)
+        for (int l = 0; l <= NM; ++l)
           if (l <= N) {
             gp = fma(hw[l], Gp[l], gp);
             gm = fma(hw[l], Gm[l], gm);
@@ -139,15 +141,23 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   }
 }
 
-void launch_multi(const MultiArgs &a, hipStream_t s, int V, int k_doubles) {
+template <int W, int NM>
+void launch_w(const MultiArgs &a, hipStream_t s, size_t shm) {
+  const int64_t pts_per_block = (int64_t)(64 / W) * kMultiWaves;
+  const int64_t blocks = (a.npts + pts_per_block - 1) / pts_per_block;
+  hipLaunchKernelGGL((multi_kernel<W, NM>), dim3((unsigned)blocks), dim3(64 * kMultiWaves), shm, s, a);
+}
+
+void launch_multi(const MultiArgs &a, hipStream_t s, int V, int k_doubles, int n_max) {
   if (a.npts <= 0) return;
   const size_t shm = sizeof(double) * (size_t)k_doubles;   // the K_a tables
+  const bool small_n = n_max <= 7;
   if (V <= 8 * 16) {   // four points per wave
-    const int64_t blocks = (a.npts + 4 * kMultiWaves - 1) / (4 * kMultiWaves);
-    hipLaunchKernelGGL(multi_kernel<16>, dim3((unsigned)blocks), dim3(64 * kMultiWaves), shm, s, a);
+    if (small_n) launch_w<16, 7>(a, s, shm);
+    else launch_w<16, kNmaxLarge>(a, s, shm);
   } else {
-    const int64_t blocks = (a.npts + kMultiWaves - 1) / kMultiWaves;
-    hipLaunchKernelGGL(multi_kernel<64>, dim3((unsigned)blocks), dim3(64 * kMultiWaves), shm, s, a);
+    if (small_n) launch_w<64, 7>(a, s, shm);
+    else launch_w<64, kNmaxLarge>(a, s, shm);
   }
 }
 

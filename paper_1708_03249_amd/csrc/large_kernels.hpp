@@ -75,12 +75,13 @@ __device__ __forceinline__ double seg_sum(double x) {
 // collected by segment sums; for the full range the closed-form recurrence
 // of Sec. IV.A.3.  Called by every lane of the wave; W >= 16 holds the main
 // rule (at most 11 points for N <= 20) and the largest correction (16).
-template <int W = 64>
+// NM bounds the order N (the register arrays' size).
+template <int W = 64, int NM = kNmaxLarge>
 __device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double T, int lane,
-                                            double (&Gp)[kNmaxLarge + 1], double (&Gm)[kNmaxLarge + 1]) {
+                                            double (&Gp)[NM + 1], double (&Gm)[NM + 1]) {
   const int N = tl->N;
 #pragma unroll
-  for (int l = 0; l <= kNmaxLarge; ++l) Gp[l] = Gm[l] = 0.0;
+  for (int l = 0; l <= NM; ++l) Gp[l] = Gm[l] = 0.0;
   if (tl->full) {
     // full range (Sec. IV.A.3): G_l = E[He_l(X)], X ~ N(m u/p0, m T/p0^2),
     // obeys G_{l+1} = ub G_l + l a G_{l-1} with a = m T/p0^2 - 1; kept as
@@ -90,19 +91,19 @@ __device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double
     Gp[0] = 1.0;
     if (N >= 1) Gp[1] = ub;
 #pragma unroll
-    for (int l = 1; l < kNmaxLarge; ++l)
+    for (int l = 1; l < NM; ++l)
       if (l + 1 <= N) Gp[l + 1] = (ub * Gp[l] + tl->sq[l] * aa * Gp[l - 1]) / tl->sq[l + 1];
 #pragma unroll
-    for (int l = 0; l <= kNmaxLarge; ++l) Gm[l] = (l & 1) ? -Gp[l] : Gp[l];
+    for (int l = 0; l <= NM; ++l) Gm[l] = (l & 1) ? -Gp[l] : Gp[l];
     return;
   }
   const double sT = sqrt(T), s = sT * tl->inv_p0, y0 = -u / sT;
-  auto accum = [&](double (&G)[kNmaxLarge + 1], double x, double wt) {
+  auto accum = [&](double (&G)[NM + 1], double x, double wt) {
     double qm = 1.0, q = x - tl->a[0];
     G[0] += wt;
     if (N >= 1) G[1] += wt * q;
 #pragma unroll
-    for (int l = 1; l < kNmaxLarge; ++l) {
+    for (int l = 1; l < NM; ++l) {
       if (l + 1 <= N) {
         const double qn = (x - tl->a[l]) * q - tl->mb[l] * qm;
         qm = q;
@@ -129,7 +130,7 @@ __device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double
     }
   }
 #pragma unroll
-  for (int l = 0; l <= kNmaxLarge; ++l) {
+  for (int l = 0; l <= NM; ++l) {
     if (l <= N) {
       Gp[l] = seg_sum<W>(Gp[l]);
       Gm[l] = seg_sum<W>(Gm[l]);

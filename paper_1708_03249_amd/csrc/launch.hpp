@@ -28,6 +28,6 @@ void launch_large(const LargeArgs &a, int adv, int H, hipStream_t s);
 
 // The mixed-quadrature (App. A) velocity-space stage: kernels_multi.hip.
 struct MultiArgs;
-void launch_multi(const MultiArgs &a, hipStream_t s, int V, int k_doubles);
+void launch_multi(const MultiArgs &a, hipStream_t s, int V, int k_doubles, int n_max);
 
 }  // namespace hhlb

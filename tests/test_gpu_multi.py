@@ -31,8 +31,12 @@ SETS = [
     ("H(6)xHH(4,p0=1.2)xL(3,p0=0.6)", [(1, 6, 5, 1.0), (0, 4, 3, 1.2), (2, 3, 2, 0.6)], [-0.4, 0.9, 0.3]),
     ("HH(8)xH(8)xH(4), V = 512", [(0, 8, 7, 1.0), (1, 8, 7, 1.0), (1, 4, 3, 1.0)], [0.2, 0.1, -0.6]),
     ("HH(2)xL(3,p0=0.6)xH(4), V = 96", [(0, 2, 1, 1.0), (2, 3, 2, 0.6), (1, 4, 3, 1.0)], [0.4, -0.7, 0.2]),
+    ("HH(12)xH(4), N = 11, V = 96", [(0, 12, 11, 1.0), (1, 4, 3, 1.0)], [0.6, -0.3]),
+    ("HH(10)xH(10)xH(2), N = 9, V = 400", [(0, 10, 9, 1.0), (1, 10, 9, 1.0), (1, 2, 1, 1.0)], [-0.2, 0.5, 0.3]),
 ]
-# sets with V <= 128 run four points per wave (16 lanes each), larger ones one
+# sets with V <= 128 run four points per wave (16 lanes each), larger ones one;
+# sets with every N_a <= 7 run the kernel with 8-entry coefficient arrays,
+# the last two the one with 21
 
 
 @pytest.fixture(scope="module", autouse=True)
