@@ -142,6 +142,11 @@ hhlb_status hhlb_state_offsets(const hhlb_solver *s, int64_t *off);
 /* The time step of each channel after resolving CFL requests:
  * dt = min(|cfl| * min_i dx_i / max_k |p_k/m|, Kn/2) when dt < 0 was given
  * (the Kn/2 cap keeps the stiff BGK term inside RK-3's stability region).
+ * The force term is not bounded by this rule: dt |g| rho(K), rho(K) the
+ * spectral radius of the force matrix, must stay well inside the stability
+ * region too.  rho(K) grows quickly with Q for the half-range sets, whose
+ * nodes crowd towards p = 0 (about 1.2e2 at Q = 40, 1.4e3 at Q = 200, 2.0e3
+ * at Q = 256); for large Q give dt explicitly (the paper's 1e-4 at Q = 200).
  * dt_out: n_ch host doubles. */
 hhlb_status hhlb_time_steps(const hhlb_solver *s, double *dt_out);
 
