@@ -41,7 +41,7 @@ constexpr int kWin = 58;       // output cells per wavefront
 // how many node-functions ahead the advection pass loads the values of y^n
 // (the mixed kernel has its own distance, HHLB_PREFETCH_MIXED)
 #ifndef HHLB_PREFETCH
-#define HHLB_PREFETCH 8
+#define HHLB_PREFETCH 16
 #endif
 constexpr int kHalo = 3;
 
