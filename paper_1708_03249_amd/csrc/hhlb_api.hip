@@ -1380,7 +1380,7 @@ namespace {
 struct MultiSet {
   std::vector<char> blob;
   int d = 0, V = 0;
-  int kdoubles = 0;   // sum of V_a^2: the K_a tables the kernel stages in LDS
+  int kdoubles = 0;   // sum of V_a multi_kcols(V_a): the padded K_a tables the kernel stages in LDS
   int nmax = 0;       // the largest equilibrium order of the axes
 };
 
@@ -1462,7 +1462,7 @@ hhlb_status multi_set(const hhlb_axis *axes, int32_t d, std::shared_ptr<const Mu
     ms->d = d;
     ms->V = V;
     for (int a = 0; a < d; ++a) {
-      ms->kdoubles += hdr.Va[a] * hdr.Va[a];
+      ms->kdoubles += hdr.Va[a] * hhlb::multi_kcols(hdr.Va[a]);
       ms->nmax = std::max(ms->nmax, (int)axes[a].N);
     }
     std::lock_guard<std::mutex> lk(g_multi_mu);

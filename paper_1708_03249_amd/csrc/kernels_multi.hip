@@ -14,7 +14,7 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   constexpr int KT = VW / W;
   __shared__ double s_f[kMultiWaves][P * VW];
   __shared__ double s_g[kMultiWaves][P * kMultiAxes * kMultiVaxis];
-  extern __shared__ double s_K[];   // the axes' K_a, row-major, back to back (sum V_a^2 doubles)
+  extern __shared__ double s_K[];   // the axes' K_a, row-major, rows padded to multi_kcols(V_a), back to back
   __shared__ double s_p[kMultiAxes * kMultiVaxis];
   __shared__ int32_t s_idx[kMultiVmax];   // packed per-axis indices of each velocity
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -23,12 +23,19 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   const int d = tm->d, V = tm->V;
   // the block stages the axes' tables (every wave takes this barrier)
   int ko[kMultiAxes] = {0, 0, 0};   // offset of K_a in s_K
+  int va[kMultiAxes] = {1, 1, 1}, kc[kMultiAxes] = {1, 1, 1}, st[kMultiAxes] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < kMultiAxes; ++a) {
     if (a >= d) break;
-    const int Va = tm->Va[a];
-    if (a + 1 < kMultiAxes) ko[a + 1] = ko[a] + Va * Va;
-    for (int t = threadIdx.x; t < Va * Va; t += 64 * kMultiWaves) s_K[ko[a] + t] = A.tab[tm->k_off[a] + t];
+    const int Va = tm->Va[a], c = multi_kcols(Va);
+    va[a] = Va;
+    kc[a] = c;
+    st[a] = tm->stride[a];
+    if (a + 1 < kMultiAxes) ko[a + 1] = ko[a] + Va * c;
+    for (int t = threadIdx.x; t < Va * c; t += 64 * kMultiWaves) {
+      const int r = t / c, col = t - r * c;
+      s_K[ko[a] + t] = col < Va ? A.tab[tm->k_off[a] + r * Va + col] : 0.0;
+    }
     if ((int)threadIdx.x < Va) s_p[a * kMultiVaxis + threadIdx.x] = A.tab[tm->p_off[a] + threadIdx.x];
   }
   {
@@ -57,6 +64,21 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   for (int t = 0; t < KT; ++t) {
     const int v = sub + W * t;
     fv[t] = v < V ? y[v] : 0.0;
+  }
+  // y^n of the stages that combine with it, loaded early so that its latency
+  // hides behind the moments and the equilibrium
+  const bool use_base = !A.rhs_only && A.a_base != 0.0;
+  double bv[KT];
+#if HHLB_MULTI_YN_EARLY
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int v = sub + W * t;
+    bv[t] = use_base && v < V ? A.base[pt * V + v] : 0.0;
+  }
+#endif
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int v = sub + W * t;
     if (v < V) sf[v] = fv[t];
   }
   double n = 0.0, mom[kMultiAxes] = {0.0, 0.0, 0.0};
@@ -117,27 +139,51 @@ __global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
   }
   __builtin_amdgcn_wave_barrier();
 
-  // force contractions, BGK and the RK-3 combination (runtime loops: the
-  // populations come back from LDS)
-  const double F0 = A.F[0], F1 = A.F[1], F2 = A.F[2];
-  for (int v = sub; v < V; v += W) {
+#if !HHLB_MULTI_YN_EARLY
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int v = sub + W * t;
+    bv[t] = use_base && v < V ? A.base[pt * V + v] : 0.0;
+  }
+#endif
+
+  // force contractions, BGK and the RK-3 combination (the populations come
+  // back from LDS).  A row of K_a is taken kMultiGroup columns at a time; the
+  // zero columns past V_a pair with the axis' last population, so the sum is
+  // the plain one over i' < V_a in the same order.
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int v = sub + W * t;
+    if (v >= V) continue;
     const double fvv = sf[v];
     const int w = s_idx[v];
     double force = 0.0, g = n;
-    for (int a = 0; a < d; ++a) {
-      const int st = tm->stride[a], Va = tm->Va[a];
-      const int i = (w >> (8 * a)) & 0xff, v0 = v - i * st;
-      const double *K = s_K + (a == 0 ? ko[0] : (a == 1 ? ko[1] : ko[2])) + i * Va;
-      double acc = 0.0;
-      for (int ip = 0; ip < Va; ++ip) acc = fma(K[ip], sf[v0 + ip * st], acc);
-      force = fma(a == 0 ? F0 : (a == 1 ? F1 : F2), acc, force);
-      g *= sg[a * kMultiVaxis + i];
+#pragma unroll
+    for (int a = 0; a < kMultiAxes; ++a) {
+      if (a < d) {
+        const int i = (w >> (8 * a)) & 0xff;
+        const double *K = s_K + ko[a] + i * kc[a];
+        const double *fa = sf + (v - i * st[a]);   // the populations along axis a through v
+        double acc = 0.0;
+        for (int ip = 0; ip < kc[a]; ip += kMultiGroup) {
+          double kk[kMultiGroup], ff[kMultiGroup];
+#pragma unroll
+          for (int u = 0; u < kMultiGroup; ++u) {
+            const int j = ip + u < va[a] ? ip + u : va[a] - 1;
+            kk[u] = K[ip + u];
+            ff[u] = fa[j * st[a]];
+          }
+#pragma unroll
+          for (int u = 0; u < kMultiGroup; ++u) acc = fma(kk[u], ff[u], acc);
+        }
+        force = fma(A.F[a], acc, force);
+        g *= sg[a * kMultiVaxis + i];
+      }
     }
     double L = -force;
     if (A.inv_Kn != 0.0) L -= (fvv - g) * (n * A.inv_Kn);
     const int64_t o = pt * V + v;
-    if (valid)
-      A.out[o] = A.rhs_only ? L : A.a_base * (A.a_base != 0.0 ? A.base[o] : 0.0) + A.b_stage * (fvv + A.dt * L);
+    if (valid) A.out[o] = A.rhs_only ? L : A.a_base * bv[t] + A.b_stage * (fvv + A.dt * L);
   }
 }
 

@@ -23,6 +23,20 @@ constexpr int kMultiVaxis = 32;    // velocities per axis
 constexpr int kMultiVmax = 512;    // velocities of the product set
 constexpr int kMultiWaves = 4;     // points per block
 
+// The kernel stages each K_a in LDS with its rows padded by zeros to a
+// multiple of HHLB_MULTI_GROUP columns, and contracts a row that many columns
+// at a time (the loads of a group issue together, one LDS wait per group).
+#ifndef HHLB_MULTI_GROUP
+#define HHLB_MULTI_GROUP 4
+#endif
+constexpr int kMultiGroup = HHLB_MULTI_GROUP;
+static_assert(kMultiGroup >= 1 && kMultiVaxis % kMultiGroup == 0, "group width");
+// 1: the kernel loads y^n with the populations; 0: just before the contractions.
+#ifndef HHLB_MULTI_YN_EARLY
+#define HHLB_MULTI_YN_EARLY 0
+#endif
+__host__ __device__ inline int multi_kcols(int Va) { return (Va + kMultiGroup - 1) / kMultiGroup * kMultiGroup; }
+
 // Tables of one product set.  The trailing doubles hold, per axis a, the
 // momenta p_a[V_a] at p_off[a], the 1-D matrix K_a[V_a][V_a] (row-major) at
 // k_off[a] and the equilibrium table HWs_a[H_a][N_a + 1] at hw_off[a]; after
