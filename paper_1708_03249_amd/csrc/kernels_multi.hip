@@ -7,8 +7,13 @@ namespace hhlb {
 // points per wave, V <= 128); each lane holds velocities sub + W t, t < 8.
 // NM bounds the axes' equilibrium orders (7 or 20: the size of the register
 // arrays of the coefficients).
+#if HHLB_MULTI_OCC
+#define HHLB_MULTI_ATTR __attribute__((amdgpu_waves_per_eu(NM <= 7 ? HHLB_MULTI_OCC : 1)))
+#else
+#define HHLB_MULTI_ATTR
+#endif
 template <int W, int NM>
-__global__ __launch_bounds__(64 * kMultiWaves) void multi_kernel(MultiArgs A) {
+__global__ __launch_bounds__(64 * kMultiWaves) HHLB_MULTI_ATTR void multi_kernel(MultiArgs A) {
   constexpr int P = 64 / W;                 // points per wave
   constexpr int VW = 8 * W;                 // largest V for this width
   constexpr int KT = VW / W;

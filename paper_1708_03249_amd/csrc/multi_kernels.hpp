@@ -35,6 +35,12 @@ static_assert(kMultiGroup >= 1 && kMultiVaxis % kMultiGroup == 0, "group width")
 #ifndef HHLB_MULTI_YN_EARLY
 #define HHLB_MULTI_YN_EARLY 0
 #endif
+// Waves per SIMD the compiler must fit the registers of the instances for
+// orders <= 7 to (0: its own choice).  Five fit the LDS of a block; the
+// W = 16 instance then keeps 96 VGPRs with a 12-byte spill.
+#ifndef HHLB_MULTI_OCC
+#define HHLB_MULTI_OCC 5
+#endif
 __host__ __device__ inline int multi_kcols(int Va) { return (Va + kMultiGroup - 1) / kMultiGroup * kMultiGroup; }
 
 // Tables of one product set.  The trailing doubles hold, per axis a, the
