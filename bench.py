@@ -249,12 +249,13 @@ def flops_per_node_update(Q=Q, N=Q - 1, nfun=2, nc=8):
     return 3 * (nfun * per_node_fn + per_cell / V)
 
 
-def measured_traffic(form="fp64"):
+def measured_traffic(form="fp64", name=None):
     """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes, if they were taken on the kernel source (the stage
-    kernel's header and the build flags) built now."""
+    WRITE_SIZE passes, if they were taken on the kernel source (the kernel's
+    sources and the build flags) built now.  `name` picks another record."""
     import hashlib
-    name = "stage_kernel_traffic.json" if form == "fp64" else f"stage_kernel_{form}_traffic.json"
+    if name is None:
+        name = "stage_kernel_traffic.json" if form == "fp64" else f"stage_kernel_{form}_traffic.json"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -429,9 +430,13 @@ def run_multi(H, torch, np, npts=1_000_000, steps=10, warmup=2):
                        f"axis), {npts} points, F = (0.3, -0.2, 0.5), Kn = 0.1, dt = 1e-3, FP64",
            "value": nu / (ms / 1e3), "unit": "node-updates/s", "ms_per_step": ms, "steps": steps,
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                        "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(name="multi_kernel_traffic.json"),
                         "kernel": "hhlb::multi_kernel (one RK-3 stage)",
-                        "algorithmic_bytes_per_node_update_per_step": 64}}
+                        "algorithmic_bytes_per_node_update_per_step": 64,
+                        "algorithmic_bytes_per_launch": 64.0 * nu / 3,
+                        "traffic_unit": "HBM bytes per launch, average over the three stages "
+                                        "(rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)"}}
     del f
     torch.cuda.empty_cache()
     return out
