@@ -6,13 +6,14 @@
 // from the point's n, u, T (App. A.2) and one 1-D contraction per axis for
 // the force (App. A.3); one RK-3 stage per launch (Eq. rk3).
 //
-// The kernel itself is in kernels_multi.hip.  One wave per point, four
-// points per block.  f is point-major (V doubles
-// per point, velocity v = (i V_y + j) V_z + k, x slowest), so a wave reads
-// its point's populations as one contiguous run; lanes hold velocities
-// lane + 64 t and the point's populations sit in LDS for the contractions.
-// The per-axis equilibrium coefficients come from axis_coeffs (the same
-// wave-level code as the 1-D large-velocity-set path).
+// The kernel itself is in kernels_multi.hip.  W lanes per point: 16 (four
+// points per wave) for V <= 128, else 64 (one point per wave); four waves
+// per block.  f is point-major (V doubles per point, velocity
+// v = (i V_y + j) V_z + k, x slowest), so a point's populations are one
+// contiguous run; lane s of a point's segment holds velocities s + W t and
+// the populations sit in LDS for the contractions.  The per-axis
+// equilibrium coefficients come from axis_coeffs (the same wave-level code
+// as the 1-D large-velocity-set path).
 #pragma once
 #include "large_kernels.hpp"
 
