@@ -70,8 +70,10 @@ __global__ __launch_bounds__(64 * kMultiWaves) HHLB_MULTI_ATTR void multi_kernel
     const int v = sub + W * t;
     fv[t] = v < V ? y[v] : 0.0;
   }
-  // y^n of the stages that combine with it, loaded early so that its latency
-  // hides behind the moments and the equilibrium
+  // y^n of the stages that combine with it, in one fixed-trip pass so that
+  // the loads issue together: here (HHLB_MULTI_YN_EARLY, latency hidden behind
+  // the moments and the equilibrium, 16 more live VGPRs) or, by default, just
+  // before the contractions
   const bool use_base = !A.rhs_only && A.a_base != 0.0;
   double bv[KT];
 #if HHLB_MULTI_YN_EARLY
