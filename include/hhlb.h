@@ -285,6 +285,24 @@ hhlb_status hhlb_multi_step(const hhlb_axis *axes, int32_t d, double *f_dev, int
                             double Kn, double dt, int32_t n_steps, void *work_dev, size_t work_bytes,
                             void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * n_steps TVD RK-3 steps as hhlb_multi_step, with the tables and the two
+ * RK stage copies in a static device array of the library instead of a
+ * workspace argument.  The array holds 32 MiB on each GPU the library runs
+ * on and stays allocated until the process ends; npts is limited to what
+ * fits: 256-byte-aligned tables plus 2 x align256(npts * V * 8) bytes
+ * (about 16000 points at V = 128).  A larger npts is HHLB_E_ARG before any
+ * side effect.  The call itself allocates no device memory and calls no
+ * allocating HIP routine; the first call with a new set of axes builds and
+ * caches that set's host tables (host memory), which hhlb_multi_nodes can
+ * do beforehand.  Every call on one GPU shares that GPU's array and leaves
+ * its contents behind: calls that overlap on one GPU (other streams or
+ * threads) race and must be ordered by the caller.  f_dev, F, Kn, dt,
+ * n_steps and hip_stream as for hhlb_multi_step. */
+hhlb_status hhlb_multi_step_noalloc(const hhlb_axis *axes, int32_t d, double *f_dev, int64_t npts,
+                                    const double *F, double Kn, double dt, int32_t n_steps, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -148,7 +148,9 @@ def lib():
         L.hhlb_multi_rhs.argtypes = [ap, i32, vp, i64, dp, ctypes.c_double, vp, vp, ctypes.c_size_t, vp]
         L.hhlb_multi_step.argtypes = [ap, i32, vp, i64, dp, ctypes.c_double, ctypes.c_double, i32, vp,
                                       ctypes.c_size_t, vp]
-        for name in ("hhlb_multi_nodes", "hhlb_multi_workspace_bytes", "hhlb_multi_rhs", "hhlb_multi_step"):
+        L.hhlb_multi_step_noalloc.argtypes = [ap, i32, vp, i64, dp, ctypes.c_double, ctypes.c_double, i32, vp]
+        for name in ("hhlb_multi_nodes", "hhlb_multi_workspace_bytes", "hhlb_multi_rhs", "hhlb_multi_step",
+                     "hhlb_multi_step_noalloc"):
             getattr(L, name).restype = ctypes.c_int32
         for name in ("hhlb_nodes", "hhlb_force_matrix", "hhlb_equilibrium", "hhlb_create",
                      "hhlb_workspace_bytes", "hhlb_bind_workspace", "hhlb_state_offsets",
@@ -233,6 +235,21 @@ class MultiSolver:
         _check(lib().hhlb_multi_step(self._ax, len(self.axes), self._f(f), self.npts, _dptr(self.F), self.Kn,
                                      float(dt), int(n_steps), ctypes.c_void_p(self.ws.data_ptr()),
                                      self.ws_bytes, ctypes.c_void_p(self.stream.cuda_stream)))
+
+
+def multi_step_noalloc(axes, f, F, Kn, dt, n_steps, stream=None):
+    """hhlb_multi_step_noalloc: n_steps RK-3 steps of the homogeneous
+    mixed-quadrature system in place on f, a (npts, V) float64 CUDA tensor,
+    with the library's static device scratch instead of a workspace."""
+    import torch
+    V = int(np.prod([a.V for a in axes]))
+    assert f.dtype == torch.float64 and f.is_cuda and f.is_contiguous() and f.numel() % V == 0
+    F = np.ascontiguousarray(np.asarray(F, dtype=np.float64))
+    assert F.shape == (len(axes),)
+    st = stream or torch.cuda.current_stream()
+    _check(lib().hhlb_multi_step_noalloc(_axes(axes), len(axes), ctypes.c_void_p(f.data_ptr()),
+                                         f.numel() // V, _dptr(F), float(Kn), float(dt), int(n_steps),
+                                         ctypes.c_void_p(st.cuda_stream)))
 
 
 class Solver:

@@ -1497,6 +1497,41 @@ hhlb::MultiArgs multi_args(const MultiSet &ms, void *work, int64_t npts, const d
   return a;
 }
 
+// The scratch of hhlb_multi_step_noalloc: the tables and the two RK stage
+// copies of the homogeneous system live in this file-scope device array
+// instead of a caller-provided workspace.  Each GPU holds its own copy until
+// the process ends.  Host code never uses the array's name as an address:
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kMultiScratchBytes = size_t(32) << 20;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kMultiScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+hhlb_status scratch_address(void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HHLB_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(HHLB_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return HHLB_OK;
+}
+
+hhlb_status multi_steps(const MultiSet &ms, double *f_dev, int64_t npts, const double *F, double Kn, double dt,
+                        int32_t n_steps, void *work_dev, hipStream_t s);
+
 }  // namespace
 
 extern "C" {
@@ -1567,7 +1602,37 @@ hhlb_status hhlb_multi_step(const hhlb_axis *axes, int32_t d, double *f_dev, int
   st = multi_launch_checks(*ms, f_dev, npts, F, Kn, work_dev, work_bytes, tb + 2 * sb);
   if (st) return st;
   if (n_steps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(HHLB_E_ARG, "need n_steps >= 0 and dt > 0");
-  hipStream_t s = (hipStream_t)hip_stream;
+  return multi_steps(*ms, f_dev, npts, F, Kn, dt, n_steps, work_dev, (hipStream_t)hip_stream);
+}
+
+hhlb_status hhlb_multi_step_noalloc(const hhlb_axis *axes, int32_t d, double *f_dev, int64_t npts,
+                                    const double *F, double Kn, double dt, int32_t n_steps, void *hip_stream) {
+  std::shared_ptr<const MultiSet> ms;
+  int st = multi_set(axes, d, ms);
+  if (st) return st;
+  if (npts < 0) return fail(HHLB_E_ARG, "npts must be >= 0");
+  const size_t tb = align256(ms->blob.size()), sb = multi_state_bytes(npts, ms->V);
+  if (tb + 2 * sb > kMultiScratchBytes)
+    return fail(HHLB_E_ARG, "npts = " + std::to_string(npts) + " needs " + std::to_string(tb + 2 * sb) +
+                                " bytes of scratch; the static scratch holds " +
+                                std::to_string(kMultiScratchBytes) + " (use hhlb_multi_step with a workspace)");
+  void *work = nullptr;
+  st = scratch_address(&work);
+  if (st) return st;
+  st = multi_launch_checks(*ms, f_dev, npts, F, Kn, work, kMultiScratchBytes, tb + 2 * sb);
+  if (st) return st;
+  if (n_steps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(HHLB_E_ARG, "need n_steps >= 0 and dt > 0");
+  return multi_steps(*ms, f_dev, npts, F, Kn, dt, n_steps, work, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+hhlb_status multi_steps(const MultiSet &msr, double *f_dev, int64_t npts, const double *F, double Kn, double dt,
+                        int32_t n_steps, void *work_dev, hipStream_t s) {
+  const MultiSet *ms = &msr;
+  const size_t tb = align256(ms->blob.size()), sb = multi_state_bytes(npts, ms->V);
   HIP_TRY(hipMemcpyAsync(work_dev, ms->blob.data(), ms->blob.size(), hipMemcpyHostToDevice, s));
   double *y1 = (double *)((char *)work_dev + tb), *y2 = (double *)((char *)work_dev + tb + sb);
   hhlb::MultiArgs a = multi_args(*ms, work_dev, npts, F, Kn);
@@ -1586,4 +1651,4 @@ hhlb_status hhlb_multi_step(const hhlb_axis *axes, int32_t d, double *f_dev, int
   return HHLB_OK;
 }
 
-}  // extern "C"
+}  // namespace
