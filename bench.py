@@ -236,23 +236,60 @@ def run_steady(H, torch, np, args):
 
 
 def flops_per_node_update(Q=Q, N=Q - 1, nfun=2, nc=8):
-    """Algorithmic floating-point operations of one node-update (both
-    functions, three stages), counting an FMA as two: WENO-5 face value
-    (3 smoothness indicators, 3 candidates, weights: 58), flux difference and
-    RK combination (6), structured force matrix (half block + rank-1:
-    2(Q+2)), collision (4); per cell and shared by its 2Q nodes: moments
-    (7 per node), equilibrium (2(Q+nc) points x (N+1) recurrence levels x 8
-    flops + 2Q (N+1) x 2 contraction)."""
+    """Floating-point operations of one node-update (both functions, three
+    stages) as the FP64 stage kernel executes them, counting an FMA as two:
+    per node and function, the lane-parallel WENO-5 face value (smoothness
+    indicators, candidates and weights of the triple decomposition: 58), flux
+    difference and RK combination (6), structured force matrix (half block
+    plus rank-1 term: 2(Q+2)) and BGK (4); per cell and shared by its 2Q
+    nodes, the moment sums (7 per node) and the equilibrium: the M = (N+2)//2
+    main points and nc correction points of each half, N+1 recurrence levels
+    of 8 flops each, then the table contraction 2Q (N+1) x 2."""
     V = 2 * Q
+    M = (N + 2) // 2
     per_node_fn = 58 + 6 + 2 * (Q + 2) + 4
-    per_cell = 7 * V + 2 * (Q + nc) * (N + 1) * 8 + V * (N + 1) * 2
+    per_cell = 7 * V + 2 * (M + nc) * (N + 1) * 8 + V * (N + 1) * 2
     return 3 * (nfun * per_node_fn + per_cell / V)
 
 
-def measured_traffic(form="fp64", name=None):
-    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes, if they were taken on the kernel source (the kernel's
-    sources and the build flags) built now.  `name` picks another record."""
+def ladder_points(counts, reach, y):
+    """Correction points per half that the equilibrium's ladder (counts,
+    reach from hhlb_equilibrium_ladder) selects for a wave whose largest
+    |y0| = |u| sqrt(m/T) is y: the smallest count whose calibrated reach
+    covers y (the top count beyond it, per panel)."""
+    if y <= 0:
+        return 0
+    for n, r in zip(counts[1:], reach[1:]):
+        if r >= y:
+            return n
+    return counts[-1] * max(1, math.ceil(y / reach[-1])) if reach[-1] > 0 else counts[-1]
+
+
+def mean_ladder_points(s, mom, np):
+    """Average correction points per half over the windows of 58 cells, from
+    the final moments: each window takes the ladder count covering its
+    largest |u|/sqrt(T)."""
+    n, u, T = mom
+    y = (u.abs() / T.clamp_min(1e-300).sqrt()).cpu().numpy()
+    counts, reach = s.equilibrium_ladder(0)
+    tot, nw = 0.0, 0
+    for k, ch in enumerate(s.channels):
+        a, b = int(s.cells[k]), int(s.cells[k + 1])
+        for i0 in range(a, b, 58):
+            tot += ladder_points(counts, reach, float(y[max(a, i0 - 3):min(b, i0 + 61)].max()))
+            nw += 1
+    return tot / max(nw, 1)
+
+
+def measured_counter(form, key):
+    """A figure (e.g. the MFMA busy fraction) from the committed rocprofv3
+    counter record of the stage kernel, if it was taken on the kernel source
+    built now; else None."""
+    rec = _profile_record(form)
+    return None if rec is None else rec.get(key)
+
+
+def _profile_record(form="fp64", name=None):
     import hashlib
     if name is None:
         name = "stage_kernel_traffic.json" if form == "fp64" else f"stage_kernel_{form}_traffic.json"
@@ -267,43 +304,98 @@ def measured_traffic(form="fp64", name=None):
             h.update(fh.read())
     if h.hexdigest() != rec.get("kernel_source_sha256"):
         return None
+    return rec
+
+
+def measured_traffic(form="fp64", name=None):
+    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes, if they were taken on the kernel source (the kernel's
+    sources and the build flags) built now.  `name` picks another record."""
+    rec = _profile_record(form, name)
+    if rec is None:
+        return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def cpu_baseline(n_channels, steps):
-    """Time the plain CPU oracle on a bounded sample of the same workload:
-    n_channels channels (one thread each) for `steps` RK-3 steps."""
+def cpu_baseline(H, torch, np, forms, steps, n_parity=4, max_threads=16):
+    """Time the plain CPU oracle on a bounded sample of the same workload and
+    check every GPU form against it on the same start.
+
+    The sample: `steps` RK-3 steps of channel 0 on one core, then of the
+    first C channels on C threads, one channel each, C the cores this process
+    may run on (sched_getaffinity), capped at max_threads (the host share of
+    one GPU).  Start: the oracle's equilibrium (1, 0, 1) times the smooth
+    modulation of the timed runs (the seeds of init_developed), and the
+    oracle's own CFL time step.  Each form then advances the first n_parity
+    channels from that same start on the GPU, and its moments are compared
+    with the oracle's after the same steps."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle as O
-    import paper_1708_03249_amd as H
     from paper_1708_03249_amd.inputs import smooth_modulation
-    chans = workload()[:n_channels]
-    dts = []
-    for ch in chans:
+    affinity = len(os.sched_getaffinity(0))
+    threads = max(1, min(affinity, max_threads))
+    chans = workload()[:max(threads, n_parity)]
+    V = 2 * Q
+
+    def ochan(ch):
         oc = O.Channel(quad=O.HALF, Q=Q, N=Q - 1, Nx=NX, adv=O.WENO5, Dt=2, A=0.9, Kn=ch.Kn,
                        g=-1.0, T_left=1.0, T_right=1.5)
-        dts.append(O.cfl_dt(oc, 0.5))
+        oc.dt = O.cfl_dt(oc, 0.5)
+        return oc
+
+    def start(c):
+        oc = ochan(chans[c])
+        f, chi = O.initial_state(oc)
+        return oc, f * smooth_modulation(2 * c, V, NX, 0.05), chi * smooth_modulation(2 * c + 1, V, NX, 0.05)
 
     def one(c):
-        ch = chans[c]
-        oc = O.Channel(quad=O.HALF, Q=Q, N=Q - 1, Nx=NX, adv=O.WENO5, Dt=2, A=0.9, Kn=ch.Kn,
-                       g=-1.0, T_left=1.0, T_right=1.5, dt=dts[c])
-        f, chi = O.initial_state(oc)
-        V = 2 * Q   # the start state of the GPU runs (init_developed)
-        f = f * smooth_modulation(2 * c, V, NX, 0.05)
-        chi = chi * smooth_modulation(2 * c + 1, V, NX, 0.05)
-        O.run(oc, steps, f, chi)
+        oc, f, chi = start(c)
+        f, chi, _ = O.run(oc, steps, f, chi)
+        return O.moments(oc, f, chi)
 
     O.lib()
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=n_channels) as ex:
-        list(ex.map(one, range(n_channels)))
-    el = time.perf_counter() - t0
-    nu = n_channels * NX * 2 * Q * steps
-    return {"value": nu / el, "unit": "node-updates/s", "cores": n_channels, "kind": "oracle",
-            "sample": f"{n_channels} of the 256 channels (Nx={NX}, HHLB(15;16), f and chi), "
-                      f"{steps} RK-3 steps each, one thread per channel, {el:.1f} s"}
+    one(0)
+    el1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        ref = list(ex.map(one, range(threads)))
+    eln = time.perf_counter() - t0
+    nu_ch = NX * V * steps
+    out = {"value": threads * nu_ch / eln, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{threads} of the 256 channels (Nx={NX}, HHLB(15;16), f and chi) on {threads} "
+                     f"threads, one channel each, {steps} RK-3 steps from the timed runs' start, "
+                     f"{eln:.1f} s",
+           "cores_available": affinity,
+           "one_core": {"value": nu_ch / el1, "unit": "node-updates/s", "cores": 1,
+                        "sample": f"channel 0, {steps} RK-3 steps, {el1:.1f} s"}}
+    # every GPU form against the oracle on the first n_parity channels
+    starts = [start(c) for c in range(n_parity)]
+    errs = {}
+    for form in forms:
+        s = H.Solver(chans[:n_parity], precision=H.PRECISIONS[form])
+        for k, (oc, _, _) in enumerate(starts):
+            assert abs(s.dt[k] - oc.dt) <= 4.5e-16 * oc.dt, (form, k, s.dt[k], oc.dt)
+        f = torch.from_numpy(np.concatenate([st[1].ravel() for st in starts])).cuda()
+        c = torch.from_numpy(np.concatenate([st[2].ravel() for st in starts])).cuda()
+        s.set_state(f, c)
+        del f, c
+        s.step(steps)
+        n, u, T = (x.cpu().numpy() for x in s.moments())
+        s.close()
+        e = {"err_n": 0.0, "err_u": 0.0, "err_T": 0.0}
+        for k in range(n_parity):
+            rn, ru, rT = ref[k]
+            a, b = k * NX, (k + 1) * NX
+            e["err_n"] = max(e["err_n"], float(np.abs(n[a:b] - rn).max() / np.abs(rn).max()))
+            e["err_u"] = max(e["err_u"], float(np.abs(u[a:b] - ru).max()))
+            e["err_T"] = max(e["err_T"], float(np.abs(T[a:b] - rT).max() / np.abs(rT).max()))
+        errs[form] = e
+        torch.cuda.empty_cache()
+    out["err_vs_oracle"] = {"channels": n_parity, "steps": steps, "start": "the timed runs' start "
+                            "(equilibrium (1, 0, 1) times the seeded smooth modulation)", "forms": errs}
+    return out
 
 
 def run_form(H, torch, np, chans, form, args):
@@ -334,30 +426,31 @@ def run_form(H, torch, np, chans, form, args):
     mass_err = float(((mass - mass0) / mass0).abs().max().item())   # relative, from the start
     node_updates = sum(c.V * c.Nx for c in chans) * args.steps
     value = node_updates / (ms / 1e3)
-    # dominant kernel: the fused stage kernel (every launch of the timed region)
+    # dominant kernel: the stage kernel (every launch of the timed region)
     n_launch = 3 * args.steps * launches
     avg_launch_s = ms / 1e3 / n_launch
     nu_per_launch = sum(c.V * c.Nx for c in chans) / launches
     bpl = bytes_per_node_update(form) / 3 * nu_per_launch
-    fpl = flops_per_node_update() / 3 * nu_per_launch
+    nc = mean_ladder_points(s, mom, np)
+    fpl = flops_per_node_update(nc=nc) / 3 * nu_per_launch
     gbs = bpl / avg_launch_s / 1e9
     tfs = fpl / avg_launch_s / 1e12
-    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tfs / FP64_VECTOR_PEAK_TFLOPS
-    if hbm_frac >= alu_frac:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_frac, 4), "traffic": measured_traffic(form)}
-        other = {"alu_fp64_tflops": round(tfs, 2), "alu_frac": round(alu_frac, 4)}
-    else:
-        roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": measured_traffic(form)}
-        other = {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4)}
+    # the scope's roof for this streaming stencil is HBM (128 B per
+    # node-update in FP64, 72 in the mixed forms); the vector-ALU fraction of
+    # the executed flop count rides along
     kname = ("hhlb::stage_kernel_half<16,2,0> (one RK-3 stage, FP64)" if form == "fp64" else
              f"hhlb::stage_kernel_mixed<16,2,0,{H.PRECISIONS[form]}> (one RK-3 stage, {form})")
-    roof["kernel"] = kname
-    roof["algorithmic_bytes_per_launch"] = bpl
-    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)"
-    roof["avg_launch_us"] = round(avg_launch_s * 1e6, 2)
-    roof.update(other)
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(form),
+            "kernel": kname, "algorithmic_bytes_per_node_update": bytes_per_node_update(form),
+            "algorithmic_bytes_per_launch": bpl,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+            "avg_launch_us": round(avg_launch_s * 1e6, 2),
+            "alu": {"flops_per_node_update": round(flops_per_node_update(nc=nc), 1),
+                    "correction_points_per_half": round(nc, 2),
+                    "achieved_tflops": round(tfs, 2), "peak_tflops": FP64_VECTOR_PEAK_TFLOPS,
+                    "frac": round(tfs / FP64_VECTOR_PEAK_TFLOPS, 4)},
+            "mfma_busy": measured_counter(form, "mfma_busy_frac")}
     rec = {"value": value, "ms_per_step": ms / args.steps, "roofline": roof, "mass_drift": mass_err,
            "wall_s": round(wall, 3), "node_updates_per_step": node_updates // args.steps}
     s.close()
@@ -365,7 +458,7 @@ def run_form(H, torch, np, chans, form, args):
 
 
 def run_ballistic(H, torch, np, nx=24, steps=2000, warmup=32):
-    """The node-parallel path on the paper's ballistic set-up (Sec. VI.D):
+    """The node-parallel path on the paper's ballistic set-up (Sec. V.E):
     HHLB(20;200), V = 400, Nx = 24 (or nx), A = 0.99, dt = 1e-4, Kn = inf, no
     chi, its eight cases (g_p in {0.1, 1} x Delta T in {0.6, 0.3, 0, -0.4})
     as one batch, from the equilibrium at rest.  The paper's dt = 1e-4 is
@@ -484,7 +577,6 @@ def main():
     ap.add_argument("--ballistic-steps", type=int, default=2000)
     ap.add_argument("--no-laguerre", action="store_true",
                     help="skip the FP64 timing of the half-range Gauss-Laguerre velocity set")
-    ap.add_argument("--cpu-channels", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
@@ -591,9 +683,10 @@ def main():
     if args.batch_channels > 0:
         out["batched"] = run_batch(H, torch, np, args)
     if not args.no_cpu_baseline:
-        print(f"[bench] cpu baseline: {args.cpu_channels} channels x {args.cpu_steps} steps",
+        print(f"[bench] cpu baseline and oracle parity: {args.cpu_steps} steps",
               file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_channels, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(H, torch, np, forms, args.cpu_steps)
+        out["err_vs_oracle"] = out["cpu_baseline"].pop("err_vs_oracle")
     print(json.dumps(out), flush=True)
 
 

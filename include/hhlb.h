@@ -117,7 +117,7 @@ hhlb_status hhlb_equilibrium(int32_t quad, int32_t Q, int32_t N, double p0, doub
  * HHLB_E_UNSUPPORTED).  Q <= 16 runs every kind in every form; Q > 16 runs
  * a node-parallel FP64 stage with N <= 20 for the half-range Gauss-Hermite
  * model up to Q = 256 and the full-range one up to Q = 512 (the HHLB(20;200)
- * and HLB(20;500) models of Sec. VI.D); other shapes are HHLB_E_UNSUPPORTED.
+ * and HLB(20;500) models of Sec. V.E); other shapes are HHLB_E_UNSUPPORTED.
  * hip_stream is a hipStream_t (NULL = default stream).  *out receives the
  * solver. */
 hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t precision,
@@ -182,21 +182,30 @@ hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps);
  *  waves_per_window: 2 = one wave per momentum half holds both f and chi of
  *                 a 64-cell window; 4 = one wave per half and function (FP64
  *                 half-range channels with chi; other classes keep 2).
+ *  step_fusion:   1 = the three stages of a step (Eq. rk3) in one launch per
+ *                 class, y^n and the stage state kept in registers over
+ *                 windows with 9-cell halos (FP64 half-range Gauss-Hermite
+ *                 classes; others keep one launch per stage); 0 = one launch
+ *                 per stage.  The stages' arithmetic is the same; results
+ *                 agree to rounding (the equilibrium's correction count is
+ *                 chosen per window of cells).
  *  ms_per_step:   filled in by hhlb_autotune (the measured time). */
 typedef struct {
   int32_t graph_steps;
   int32_t class_streams;
   int32_t xcd_map;
   int32_t waves_per_window;
+  int32_t step_fusion;
   float ms_per_step;
 } hhlb_tuning;
 
-/* Set / read the launch configuration (defaults: 0, 0, 1, 2). */
+/* Set / read the launch configuration (defaults: 0, 0, 1, 2, 0). */
 hhlb_status hhlb_set_tuning(hhlb_solver *s, const hhlb_tuning *t);
 hhlb_status hhlb_get_tuning(const hhlb_solver *s, hhlb_tuning *t);
 
 /* Autotuner: times trial_steps steps of every candidate configuration
- * (waves_per_window in {2, 4} when a class has the four-wave kernel; direct
+ * (step_fusion in {0, 1} when a class has the fused-step kernel;
+ * waves_per_window in {2, 4} when a class has the four-wave kernel; direct
  * launches with class_streams in {0, 1} -- 1 only when there are several
  * classes -- and graphs of 16 steps; each with xcd_map in {1, 0}) on the
  * solver's own channels and keeps the fastest; *best_out (may be NULL)
@@ -238,6 +247,26 @@ hhlb_status hhlb_diagnostics(hhlb_solver *s, double *n_wall_dev, double *mass_de
 hhlb_status hhlb_launch_info(const hhlb_solver *s, int32_t *launches_per_stage,
                              int64_t *windows_total);
 
+/* The correction ladder of the half-range equilibrium of channel `channel`
+ * (Sec. IV.B.3 evaluated by a change of variables: an M-point half-range
+ * Gauss rule plus a Gauss-Legendre correction over [y0, 0]): counts[8]
+ * point counts and reach[8] the largest |y0| each count was calibrated to
+ * cover (host arrays).  A wave uses the smallest count whose reach covers
+ * its largest |y0|.  Full-range channels are HHLB_E_UNSUPPORTED. */
+hhlb_status hhlb_equilibrium_ladder(const hhlb_solver *s, int32_t channel, int32_t *counts, double *reach);
+
+/* Number of equilibrium evaluations (a wavefront's 64 cells of one momentum
+ * half in one stage; one cell for Q > 16) since hhlb_bind_workspace whose
+ * largest |y0| = |u| sqrt(m/T) lay beyond the range the correction ladder
+ * of the half-range equilibrium (Sec. IV.B.3, evaluated by a change of
+ * variables) was calibrated for on the host (|y0| <= 1 for the Hermite
+ * sets).  Such evaluations split the correction integral into equal panels
+ * of the calibrated width, up to 64 panels (|y0| up to 64 times that
+ * range).  Synchronises the solver's stream; *count is a host int64. */
+hhlb_status hhlb_wide_equilibrium_count(const hhlb_solver *s, int64_t *count);
+
+/* Wait for the solver's streams, then release its host tables, graphs,
+ * streams and events (the caller's workspace is not freed). */
 hhlb_status hhlb_destroy(hhlb_solver *s);
 
 /* Text of the last error on this thread ("" if none); valid until the next

@@ -1,5 +1,5 @@
 """Closed-form stationary solution of the force-driven channel in the
-ballistic regime (Kn = inf), Sec. VI.C of the paper: the kinetic solution
+ballistic regime (Kn = inf), Sec. V.D of the paper: the kinetic solution
 Eq. (f_bal), the density Eq. (bal_n) and the temperature Eq. (bal_temp), and
 the convergence measure Eq. (epsmax).
 

@@ -38,6 +38,7 @@ typedef __float128 qf;
 
 #define ORC_QMAX 256           /* largest quadrature order the tables accept  */
 #define ORC_VMAX (2 * ORC_QMAX)
+#define ORC_NEQ 21             /* equilibrium orders N <= 20 (the paper's largest) */
 #define ORC_QMONO 16           /* half-range Hermite: monomial construction up to
                                   this Q, the three-term recurrence beyond it   */
 #define ORC_QLAG 32            /* largest half-range Laguerre order            */
@@ -89,6 +90,12 @@ typedef struct {
   double K[ORC_VMAX * ORC_VMAX];     /* force matrix, row-major K[k*V + k']   */
   double Kin[ORC_VMAX * ORC_VMAX];   /* half-range: within-half sum term only */
   double Kd[ORC_VMAX * ORC_VMAX];    /* half-range: the delta-term part only  */
+  /* full range: He_l(p_k/p0) / l! at every node for the equilibrium orders
+   * l <= min(Q-1, 20), computed once (the per-cell sums of Eq. (H_gk) read
+   * them instead of re-running the recurrence) */
+  qf heq[ORC_NEQ][ORC_VMAX];
+  /* full range: the coefficients l!/(2^s s! (l-2s)!) of G_l, Eq. (H_gk) */
+  qf gco[ORC_NEQ][ORC_NEQ];
 } orc_tables;
 
 /* Moments of the half-range weight omega(z) = exp(-z^2/2)/sqrt(2 pi) on
@@ -606,7 +613,18 @@ static int build_tables(orc_tables *t, int quad, int Q, double p0) {
    * c[l][s] up to l = Q + 1; the full-range roots cost O(Q^3) */
   if (quad == ORC_HALF_LAGUERRE && Q > ORC_QLAG) return -1;
   if (quad == ORC_HALF) return build_half(t, Q, p0);
-  if (quad == ORC_FULL) return Q > g_qfmono ? build_full_rec(t, Q, p0) : build_full(t, Q, p0);
+  if (quad == ORC_FULL) {
+    int r = Q > g_qfmono ? build_full_rec(t, Q, p0) : build_full(t, Q, p0);
+    if (r) return r;
+    qf lf[ORC_NEQ + 1];
+    lf[0] = 1;
+    for (int l = 1; l <= ORC_NEQ; ++l) lf[l] = lf[l - 1] * l;
+    for (int l = 0; l < ORC_NEQ && l < Q; ++l)
+      for (int k = 0; k < t->V; ++k) t->heq[l][k] = he_eval(l, k < t->H ? t->z[k] : -t->z[k - t->H]) / lf[l];
+    for (int l = 0; l < ORC_NEQ; ++l)
+      for (int j = 0; 2 * j <= l; ++j) t->gco[l][j] = lf[l] / (powq(2, j) * lf[j] * lf[l - 2 * j]);
+    return 0;
+  }
   if (quad == ORC_HALF_LAGUERRE) return build_half_laguerre(t, Q, p0);
   return -1;
 }
@@ -661,20 +679,20 @@ static void eq_full(const orc_tables *t, int N, qf u, qf T, double *gout) {
   const qf m = 1;
   qf p0 = (qf)t->p0;
   qf a = m * T / (p0 * p0) - 1, b = m * u / p0;
-  qf G[ORC_QMAX + 2], lf[ORC_QMAX + 2];
+  qf G[ORC_QMAX + 2], lf[ORC_QMAX + 2], ap[ORC_NEQ], bp[ORC_NEQ];
   lf[0] = 1;
   for (int l = 1; l <= N + 1; ++l) lf[l] = lf[l - 1] * l;
+  ap[0] = bp[0] = 1;
+  for (int s = 1; s <= N; ++s) { ap[s] = ap[s - 1] * a; bp[s] = bp[s - 1] * b; }
   for (int l = 0; l <= N; ++l) {
     qf acc = 0;
-    for (int s = 0; 2 * s <= l; ++s)
-      acc += lf[l] / (powq(2, s) * lf[s] * lf[l - 2 * s]) * powq(a, s) * powq(b, l - 2 * s);
+    for (int s = 0; 2 * s <= l; ++s) acc += t->gco[l][s] * ap[s] * bp[l - 2 * s];
     G[l] = acc;
   }
   int H = t->H;
   for (int k = 0; k < t->V; ++k) {
-    qf z = (k < H) ? t->z[k] : -t->z[k - H];
     qf acc = 0;
-    for (int l = 0; l <= N; ++l) acc += G[l] * he_eval(l, z) / lf[l];
+    for (int l = 0; l <= N; ++l) acc += G[l] * t->heq[l][k];
     gout[k] = (double)(t->w[k % H] * acc);
   }
 }
@@ -744,22 +762,26 @@ static double upwind3_face(double b, double c, double d) {
 
 /* xf[j] = position of face j+1/2 for j = 0..Nx (paper's i = j), dx[i-1] for
  * cells i = 1..Nx, xc[i-1] cell centres x(eta_i). */
+/* Faces x(eta_{i+1/2}), widths dx_i = x(eta_{i+1/2}) - x(eta_{i-1/2}) and
+ * centres x(eta_i) of Eqs. (x_eta), (etai), evaluated in __float128 and
+ * rounded once: the width of a cell next to a wall is the difference of two
+ * faces near +-L/2, which in double would keep only about 12 digits of it. */
 static void grid(const orc_channel *ch, double *xf, double *dx, double *xc) {
   int Nx = ch->Nx;
-  double L = ch->L, A = ch->A;
-  if (A == 0.0) {
-    for (int j = 0; j <= Nx; ++j) xf[j] = -L / 2 + L * j / Nx;
-    for (int i = 1; i <= Nx; ++i) if (xc) xc[i - 1] = -L / 2 + L * (i - 0.5) / Nx;
+  qf L = ch->L, A = ch->A;
+  qf *f = (qf *)malloc(sizeof(qf) * (Nx + 1));
+  if (A == 0) {
+    for (int j = 0; j <= Nx; ++j) f[j] = -L / 2 + L * j / Nx;
+    for (int i = 1; i <= Nx; ++i) if (xc) xc[i - 1] = (double)(-L / 2 + L * (i - 0.5Q) / Nx);
   } else {
-    double deta = 2.0 / Nx * atanh(A);
-    for (int j = 0; j <= Nx; ++j) {
-      double eta = (j + 0.5 - (Nx + 1) / 2.0) * deta;
-      xf[j] = L / (2 * A) * tanh(eta);
-    }
+    qf deta = 2 * atanhq(A) / Nx;
+    for (int j = 0; j <= Nx; ++j) f[j] = L / (2 * A) * tanhq((j + 0.5Q - (Nx + 1) / 2.0Q) * deta);
     for (int i = 1; i <= Nx; ++i)
-      if (xc) xc[i - 1] = L / (2 * A) * tanh((i - (Nx + 1) / 2.0) * deta);
+      if (xc) xc[i - 1] = (double)(L / (2 * A) * tanhq((i - (Nx + 1) / 2.0Q) * deta));
   }
-  for (int i = 1; i <= Nx; ++i) dx[i - 1] = xf[i] - xf[i - 1];
+  for (int j = 0; j <= Nx; ++j) xf[j] = (double)f[j];
+  for (int i = 1; i <= Nx; ++i) dx[i - 1] = (double)(f[i] - f[i - 1]);
+  free(f);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -913,6 +935,7 @@ static int ctx_init(orc_ctx *c, const orc_channel *ch) {
   if (ch->adv != ORC_WENO5 && ch->adv != ORC_UPWIND3) return -1;
   if (build_tables(&c->t, ch->quad, ch->Q, ch->p0)) return -1;
   if (c->t.rec && ch->N > 20) return -1;   /* recurrence rules keep h_0..h_21 in monomials */
+  if (c->t.quad == ORC_FULL && ch->N >= ORC_NEQ) return -1;   /* He_l tabulated for l <= 20 */
   c->V = c->t.V; c->H = c->t.H; c->N = ch->N; c->Nx = ch->Nx; c->Ne = ch->Nx + 6;
   c->xf = (double *)malloc(sizeof(double) * (ch->Nx + 1));
   c->dx = (double *)malloc(sizeof(double) * ch->Nx);
@@ -982,7 +1005,10 @@ int orc_set_qmono(int qmono) {
 int orc_equilibrium(int quad, int Q, int N, double p0, double n, double u, double T, double *feq) {
   if (N < 0 || N >= Q || !(T > 0)) return -1;
   orc_tables *t = (orc_tables *)malloc(sizeof(orc_tables));
-  if (build_tables(t, quad, Q, p0) || (t->rec && N > 20)) { free(t); return -1; }
+  if (build_tables(t, quad, Q, p0) || (t->rec && N > 20) || (t->quad == ORC_FULL && N >= ORC_NEQ)) {
+    free(t);
+    return -1;
+  }
   equilibrium(t, N, u, T, feq);
   for (int k = 0; k < t->V; ++k) feq[k] *= n;
   int V = t->V;

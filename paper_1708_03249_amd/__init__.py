@@ -38,12 +38,12 @@ class HHLBError(RuntimeError):
 class _CTuning(ctypes.Structure):
     _fields_ = [("graph_steps", ctypes.c_int32), ("class_streams", ctypes.c_int32),
                 ("xcd_map", ctypes.c_int32), ("waves_per_window", ctypes.c_int32),
-                ("ms_per_step", ctypes.c_float)]
+                ("step_fusion", ctypes.c_int32), ("ms_per_step", ctypes.c_float)]
 
     def as_dict(self):
         return {"graph_steps": self.graph_steps, "class_streams": self.class_streams,
                 "xcd_map": self.xcd_map, "waves_per_window": self.waves_per_window,
-                "ms_per_step": self.ms_per_step}
+                "step_fusion": self.step_fusion, "ms_per_step": self.ms_per_step}
 
 
 class _CChannel(ctypes.Structure):
@@ -138,6 +138,8 @@ def lib():
         L.hhlb_diagnostics.argtypes = [vp, vp, vp, vp, vp]
         L.hhlb_launch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.hhlb_destroy.argtypes = [vp]
+        L.hhlb_wide_equilibrium_count.argtypes = [vp, ctypes.POINTER(i64)]
+        L.hhlb_equilibrium_ladder.argtypes = [vp, i32, ctypes.POINTER(i32), dp]
         L.hhlb_set_graph_steps.argtypes = [vp, i32]
         L.hhlb_set_tuning.argtypes = [vp, ctypes.POINTER(_CTuning)]
         L.hhlb_get_tuning.argtypes = [vp, ctypes.POINTER(_CTuning)]
@@ -157,7 +159,7 @@ def lib():
                      "hhlb_time_steps", "hhlb_set_state", "hhlb_init_equilibrium", "hhlb_step",
                      "hhlb_get_state", "hhlb_moments", "hhlb_diagnostics", "hhlb_launch_info",
                      "hhlb_destroy", "hhlb_set_graph_steps", "hhlb_set_tuning", "hhlb_get_tuning",
-                     "hhlb_autotune"):
+                     "hhlb_autotune", "hhlb_wide_equilibrium_count", "hhlb_equilibrium_ladder"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -308,8 +310,9 @@ class Solver:
     def step(self, n_steps: int):
         _check(lib().hhlb_step(self.h, int(n_steps)))
 
-    def set_tuning(self, graph_steps=0, class_streams=0, xcd_map=1, waves_per_window=2):
-        t = _CTuning(int(graph_steps), int(class_streams), int(xcd_map), int(waves_per_window), 0.0)
+    def set_tuning(self, graph_steps=0, class_streams=0, xcd_map=1, waves_per_window=2, step_fusion=0):
+        t = _CTuning(int(graph_steps), int(class_streams), int(xcd_map), int(waves_per_window),
+                     int(step_fusion), 0.0)
         _check(lib().hhlb_set_tuning(self.h, ctypes.byref(t)))
 
     def tuning(self):
@@ -352,6 +355,20 @@ class Solver:
         if residual:
             return nw.view(nch, 2), mass, bad, res
         return nw.view(nch, 2), mass, bad
+
+    def wide_equilibrium_count(self) -> int:
+        """Equilibrium evaluations whose |u|/sqrt(T) lay beyond the correction
+        ladder's calibrated range (and ran the composite rule); syncs."""
+        c = ctypes.c_int64()
+        _check(lib().hhlb_wide_equilibrium_count(self.h, ctypes.byref(c)))
+        return c.value
+
+    def equilibrium_ladder(self, channel: int = 0):
+        """(counts[8], reach[8]) of the channel's correction ladder."""
+        n = (ctypes.c_int32 * 8)()
+        r = np.zeros(8)
+        _check(lib().hhlb_equilibrium_ladder(self.h, int(channel), n, _dptr(r)))
+        return list(n), r
 
     def launch_info(self):
         a, b = ctypes.c_int32(), ctypes.c_int64()

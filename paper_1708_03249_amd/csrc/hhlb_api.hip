@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/hhlb.h"
+#include "fused_kernels.hpp"
 #include "large_kernels.hpp"
 #include "launch.hpp"
 #include "multi_kernels.hpp"
@@ -241,8 +242,11 @@ struct ModelClass {
   hhlb::DevTables dev;
   Launcher launch = nullptr;    // two waves per window
   Launcher launch4 = nullptr;   // four waves per window (FP64, f and chi), if built
+  Launcher fused = nullptr;     // one launch per RK-3 step (FP64 half range), if built
   std::vector<hhlb::DevWindow> windows;
   size_t win_off = 0;  // byte offset in workspace
+  std::vector<hhlb::DevWindow> fwindows;   // the fused kernel's windows (9-cell halos)
+  size_t fwin_off = 0;
   // Q > 16 (half-range Hermite, FP64): the node-parallel stage, whose tables
   // (DevLarge, then KinT and HWs) live in their own workspace block
   bool large = false;
@@ -266,7 +270,7 @@ struct hhlb_solver {
   hipStream_t stream = nullptr;
   // workspace layout (byte offsets)
   size_t o_tables = 0, o_chans = 0, o_chclass = 0, o_V = 0, o_dx = 0, o_invdx = 0, o_gw = 0,
-         o_nwall = 0, o_feq = 0, o_feqoff = 0, o_flag = 0, o_state = 0, bytes = 0;
+         o_nwall = 0, o_feq = 0, o_feqoff = 0, o_flag = 0, o_wide = 0, o_state = 0, bytes = 0;
   // large classes: per-cell output of the cell phase and the stage's wall densities
   size_t o_cell = 0, o_lnw = 0;
   bool any_large = false;
@@ -289,14 +293,31 @@ struct hhlb_solver {
   bool flag_pending = false;
   // launch configuration (hhlb_set_tuning / hhlb_autotune): direct launches,
   // classes one after the other, XCD-aware window mapping by default
-  hhlb_tuning tuning = {0, 0, 1, 2, 0.0f};
+  hhlb_tuning tuning = {0, 0, 1, 2, 0, 0.0f};
   std::vector<hipStream_t> cstreams;   // one per model class (class_streams)
   std::vector<hipEvent_t> cjoin;
   hipEvent_t cfork = nullptr;
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t gexec_k[2] = {nullptr, nullptr}, gexec_1[2] = {nullptr, nullptr};  // per starting parity
+  bool has_graphs() const {
+    for (int p = 0; p < 2; ++p)
+      if (gexec_k[p] || gexec_1[p]) return true;
+    return false;
+  }
+  // Wait until nothing the solver enqueued is in flight: the caller's
+  // stream (graph replays are joined back into it), the replay stream and
+  // the class streams.
+  void quiesce() {
+    (void)hipStreamSynchronize(stream);
+    if (gstream) (void)hipStreamSynchronize(gstream);
+    for (hipStream_t st : cstreams) (void)hipStreamSynchronize(st);
+  }
+  // Graph executables are destroyed only once no replay of them can still
+  // be queued or running.
   void drop_graphs() {
+    if (!has_graphs()) return;
+    quiesce();
     for (int p = 0; p < 2; ++p) {
       if (gexec_k[p]) (void)hipGraphExecDestroy(gexec_k[p]);
       if (gexec_1[p]) (void)hipGraphExecDestroy(gexec_1[p]);
@@ -304,6 +325,7 @@ struct hhlb_solver {
     }
   }
   ~hhlb_solver() {
+    quiesce();
     drop_graphs();
     for (hipEvent_t e : cjoin) (void)hipEventDestroy(e);
     for (hipStream_t st : cstreams) (void)hipStreamDestroy(st);
@@ -343,18 +365,24 @@ hhlb_status check_channel(const hhlb_channel &c, int idx) {
   return HHLB_OK;
 }
 
-// Grid of Eqs. (x_eta) and (etai): faces, widths.
+// Grid of Eqs. (x_eta) and (etai): the cell widths
+// dx_i = x(eta_{i+1/2}) - x(eta_{i-1/2}).  On the stretched grid the
+// difference of the two faces is taken in closed form,
+// tanh a - tanh b = sinh(a - b) / (cosh a cosh b), which keeps full relative
+// accuracy for the thin cells next to the walls (the difference of faces near
+// +-L/2 would cancel).
 void make_grid(const hhlb_channel &c, std::vector<double> &dx) {
   const int Nx = c.Nx;
   dx.resize(Nx);
-  std::vector<long double> xf(Nx + 1);
   if (c.stretch_A == 0.0) {
-    for (int j = 0; j <= Nx; ++j) xf[j] = -(long double)c.L / 2 + (long double)c.L * j / Nx;
+    for (int i = 0; i < Nx; ++i) dx[i] = (double)((long double)c.L / Nx);
   } else {
-    long double A = c.stretch_A, deta = 2.0L / Nx * atanhl(A);
-    for (int j = 0; j <= Nx; ++j) xf[j] = c.L / (2 * A) * tanhl((j + 0.5L - (Nx + 1) / 2.0L) * deta);
+    const long double A = c.stretch_A, deta = 2.0L / Nx * atanhl(A), sd = sinhl(deta);
+    for (int i = 0; i < Nx; ++i) {
+      const long double a = (i + 1 - Nx / 2.0L) * deta, b = (i - Nx / 2.0L) * deta;   // faces i+1/2, i-1/2
+      dx[i] = (double)((long double)c.L / (2 * A) * sd / (coshl(a) * coshl(b)));
+    }
   }
-  for (int i = 0; i < Nx; ++i) dx[i] = (double)(xf[i + 1] - xf[i]);
 }
 
 // Round-to-nearest-even conversions of FP32 values, as the matrix-core
@@ -450,15 +478,25 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
       d.irsc[k] = std::ldexp(1.0f, e);
       for (int j = 0; j < r.H; ++j) d.Ks16[k * r.H + j] = d.Ks[k * r.H + j] * rs;
     }
+    // the operands' high part rounds the table entry, the low part rounds
+    // the (exactly representable) remainder
     for (int j = 0; j < r.H; ++j) {
-      long double c = 0;
+      long double c = 0, cl = 0;
       for (int k = 0; k < r.H; ++k) {
-        float kr = d.Ks[k * r.H + j];
-        if (precision == HHLB_MIXED_BF16) kr = round_bf16(kr);
-        else if (precision == HHLB_MIXED_F16) kr = round_f16(d.Ks16[k * r.H + j]) * d.irsc[k];
-        c += r.w[k] * (long double)kr;
+        float kh = d.Ks[k * r.H + j], kl = 0.0f;
+        if (precision == HHLB_MIXED_BF16) {
+          kh = round_bf16(d.Ks[k * r.H + j]);
+          kl = round_bf16(d.Ks[k * r.H + j] - kh);
+        } else if (precision == HHLB_MIXED_F16) {
+          const float x = d.Ks16[k * r.H + j], xh = round_f16(x);
+          kh = xh * d.irsc[k];
+          kl = round_f16(x - xh) * d.irsc[k];
+        }
+        c += r.w[k] * (long double)kh;
+        cl += r.w[k] * (long double)kl;
       }
       d.crs[j] = (float)c;
+      d.crs_lo[j] = (float)cl;
     }
   }
   // correction ladder (half range): point counts and the |y0| each covers
@@ -731,6 +769,8 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
           mc.launch = lk->second;
           auto lk4 = launchers().find({kq, h.Q, nf, h.adv, precision, 4});
           if (lk4 != launchers().end()) mc.launch4 = lk4->second;
+          auto lkf = launchers().find({kq, h.Q, nf, h.adv, precision, 1});
+          if (lkf != launchers().end() && kq == HHLB_HALF_HERMITE) mc.fused = lkf->second;
           st = cached_tables(h, N, precision, mc.rule, mc.dev);
           if (st) return st;
         }
@@ -799,6 +839,8 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
       d.inv_1pDt = 1.0 / (1.0 + h.transverse_dof);
       s->dch.push_back(d);
       for (int i0 = 0; i0 < h.Nx; i0 += hhlb::kWin) mc.windows.push_back({c, i0});
+      if (mc.fused)
+        for (int i0 = 0; i0 < h.Nx; i0 += hhlb::fused_window_cells(i0, h.Nx)) mc.fwindows.push_back({c, i0});
     }
     // workspace layout
     size_t o = 0;
@@ -807,7 +849,10 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
     s->o_chans = take(sizeof(hhlb::DevChannel) * n_ch);
     s->o_chclass = take(sizeof(int32_t) * n_ch);
     s->o_V = take(sizeof(int32_t) * n_ch);
-    for (auto &mc : s->classes) mc.win_off = take(sizeof(hhlb::DevWindow) * mc.windows.size());
+    for (auto &mc : s->classes) {
+      mc.win_off = take(sizeof(hhlb::DevWindow) * mc.windows.size());
+      mc.fwin_off = take(sizeof(hhlb::DevWindow) * mc.fwindows.size());
+    }
     s->o_dx = take(sizeof(double) * s->total_cells);
     s->o_invdx = take(sizeof(double) * s->total_cells);
     s->o_gw = take(sizeof(double) * s->gw.size());
@@ -817,6 +862,7 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
     s->o_feq = take(sizeof(double) * feq_total);
     s->o_feqoff = take(sizeof(int32_t) * n_ch);
     s->o_flag = take(sizeof(int32_t));
+    s->o_wide = take(sizeof(unsigned long long));
     for (auto &mc : s->classes)
       if (mc.large) mc.lbl_off = take(mc.lblob.size());
     if (s->any_large) {
@@ -866,6 +912,9 @@ hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr) {
   for (auto &mc : s->classes) {
     HIP_TRY(hipMemcpyAsync(ws + mc.win_off, mc.windows.data(), sizeof(hhlb::DevWindow) * mc.windows.size(),
                            hipMemcpyHostToDevice, s->stream));
+    if (!mc.fwindows.empty())
+      HIP_TRY(hipMemcpyAsync(ws + mc.fwin_off, mc.fwindows.data(), sizeof(hhlb::DevWindow) * mc.fwindows.size(),
+                             hipMemcpyHostToDevice, s->stream));
     if (mc.large)
       HIP_TRY(hipMemcpyAsync(ws + mc.lbl_off, mc.lblob.data(), mc.lblob.size(), hipMemcpyHostToDevice, s->stream));
   }
@@ -879,6 +928,7 @@ hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr) {
                          hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemsetAsync(ws + s->o_nwall, 0, sizeof(double) * 2 * n_ch, s->stream));
   HIP_TRY(hipMemsetAsync(ws + s->o_flag, 0, sizeof(int32_t), s->stream));
+  HIP_TRY(hipMemsetAsync(ws + s->o_wide, 0, sizeof(unsigned long long), s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->ws = ws;
   s->flag_pending = false;
@@ -888,11 +938,14 @@ hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr) {
   const size_t stride = align256(s->esize * s->total_state);
   auto next = [&](size_t bytes) { char *p = st; st += align256(bytes); return (void *)p; };
   const size_t vb = s->esize * s->total_state, lb = sizeof(int16_t) * s->total_state;
+  // FP64: y^n ping-pongs between A and B (every step writes the other copy)
+  // and C holds the second stage; mixed: (hi, lo) ping-pong, B and C the
+  // stage increments
   s->hiF[0] = next(vb); s->fB = next(vb); s->fC = next(vb);
-  s->hiF[1] = s->mixed() ? next(vb) : nullptr;
+  s->hiF[1] = s->mixed() ? next(vb) : s->fB;
   if (s->has_chi) {
     s->hiC[0] = next(vb); s->cB = next(vb); s->cC = next(vb);
-    s->hiC[1] = s->mixed() ? next(vb) : nullptr;
+    s->hiC[1] = s->mixed() ? next(vb) : s->cB;
   } else {
     s->hiC[0] = s->hiC[1] = s->cB = s->cC = nullptr;
   }
@@ -1009,6 +1062,7 @@ void enqueue_class_stage(hhlb_solver *s, size_t ci, int stage, const void *inf, 
     la.cell = (double *)(s->ws + s->o_cell);
     la.lnw = (double *)(s->ws + s->o_lnw);
     la.nwall = (double *)(s->ws + s->o_nwall);
+    la.wide = (unsigned long long *)(s->ws + s->o_wide);
     la.nfun = mc.Dt > 0 ? 2 : 1;
     la.xcd_map = s->tuning.xcd_map;
     hhlb::launch_large(la, mc.adv, mc.rule.H, stream);
@@ -1029,9 +1083,32 @@ void enqueue_class_stage(hhlb_solver *s, size_t ci, int stage, const void *inf, 
   a.a_base = a_base;
   a.b_stage = b_stage;
   a.nwall = (double *)(s->ws + s->o_nwall);
+  a.wide = (unsigned long long *)(s->ws + s->o_wide);
   a.lo_in_f = lo_in_f; a.lo_in_c = lo_in_c;
   a.lo_out_f = lo_out_f; a.lo_out_c = lo_out_c;
   (s->tuning.waves_per_window == 4 && mc.launch4 ? mc.launch4 : mc.launch)(a, stream);
+}
+
+// One whole RK-3 step of model class ci in one launch (FP64 half-range
+// classes with a fused-step kernel): y^n from (inf, inc), y^{n+1} to (outf, outc).
+void enqueue_class_fused(hhlb_solver *s, size_t ci, const void *inf, const void *inc, void *outf, void *outc,
+                         hipStream_t stream) {
+  ModelClass &mc = s->classes[ci];
+  hhlb::StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables) + ci;
+  a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
+  a.wins = (const hhlb::DevWindow *)(s->ws + mc.fwin_off);
+  a.nwin = (int32_t)mc.fwindows.size();
+  a.stage = 2;
+  a.xcd_map = s->tuning.xcd_map;
+  a.inv_dx = (const double *)(s->ws + s->o_invdx);
+  a.gw = (const double *)(s->ws + s->o_gw);
+  a.in_f = inf; a.in_c = inc;
+  a.out_f = outf; a.out_c = outc;
+  a.nwall = (double *)(s->ws + s->o_nwall);
+  a.wide = (unsigned long long *)(s->ws + s->o_wide);
+  mc.fused(a, stream);
 }
 
 // One RK stage of every class on one stream.
@@ -1043,19 +1120,26 @@ void enqueue_stage(hhlb_solver *s, int stage, const void *inf, const void *inc, 
 
 // n_steps RK-3 steps (Eq. rk3) of class ci on one stream, starting from the
 // solver's current state parity (left unchanged).
-//  FP64: stage 1 A -> B, stage 2 B -> C, stage 3 C -> A (pointwise in y^n,
-//        so in place is safe).
+//  FP64, y^n in copy p of the pair (A, B), q = 1 - p: stage 1 p -> q,
+//        stage 2 (q, p) -> C, stage 3 (C, p) -> q (y1 in q is dead by then);
+//        or, with step fusion, one launch p -> q.
 //  Mixed: stage 1 hi -> d1 (B), stage 2 (hi, d1) -> d2 (C), stage 3
-//        (hi, lo, d2) -> the other (hi, lo) copy; the parity then flips.
+//        (hi, lo, d2) -> the other (hi, lo) copy.
+// Every step moves y^n to the other copy: the parity flips.
 void enqueue_class_steps(hhlb_solver *s, size_t ci, int64_t n_steps, hipStream_t stream) {
   const int par0 = s->par;
   for (int64_t step = 0; step < n_steps; ++step) {
+    const int p = s->par, q = p ^ 1;
     if (!s->mixed()) {
-      enqueue_class_stage(s, ci, 0, s->fA(), s->cA(), s->fB, s->cB, 0.0, 1.0, stream);
-      enqueue_class_stage(s, ci, 1, s->fB, s->cB, s->fC, s->cC, 0.75, 0.25, stream);
-      enqueue_class_stage(s, ci, 2, s->fC, s->cC, s->fA(), s->cA(), 1.0 / 3.0, 2.0 / 3.0, stream);
+      if (s->tuning.step_fusion && s->classes[ci].fused) {
+        enqueue_class_fused(s, ci, s->hiF[p], s->hiC[p], s->hiF[q], s->hiC[q], stream);
+      } else {
+        enqueue_class_stage(s, ci, 0, s->hiF[p], s->hiC[p], s->hiF[q], s->hiC[q], 0.0, 1.0, stream);
+        enqueue_class_stage(s, ci, 1, s->hiF[q], s->hiC[q], s->fC, s->cC, 0.75, 0.25, stream);
+        enqueue_class_stage(s, ci, 2, s->fC, s->cC, s->hiF[q], s->hiC[q], 1.0 / 3.0, 2.0 / 3.0, stream);
+      }
+      s->par = q;
     } else {
-      const int p = s->par, q = p ^ 1;
       enqueue_class_stage(s, ci, 0, nullptr, nullptr, s->fB, s->cB, 0.0, 1.0, stream);
       enqueue_class_stage(s, ci, 1, s->fB, s->cB, s->fC, s->cC, 0.75, 0.25, stream);
       enqueue_class_stage(s, ci, 2, s->fC, s->cC, s->hiF[q], s->hiC[q], 1.0 / 3.0, 2.0 / 3.0, stream,
@@ -1079,22 +1163,25 @@ hhlb_status enqueue_steps(hhlb_solver *s, int64_t n_steps, hipStream_t stream, b
     const int par0 = s->par;
     for (int64_t step = 0; step < n_steps; ++step) {
       for (size_t ci = 0; ci < nc; ++ci) enqueue_class_steps(s, ci, 1, stream);
-      if (s->mixed()) s->par ^= 1;
+      s->par ^= 1;
     }
-    if (!s->mixed()) s->par = par0;
+    (void)par0;
     return HHLB_OK;
   }
-  if (s->cstreams.size() < nc) {
-    while (s->cstreams.size() < nc) {
-      hipStream_t st;
-      HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-      s->cstreams.push_back(st);
-      hipEvent_t ev;
-      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      s->cjoin.push_back(ev);
+  // one stream and one join event per class, created and kept in pairs
+  while (s->cstreams.size() < nc) {
+    hipStream_t st = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(st);
+      return fail(HHLB_E_HIP, std::string("hipEventCreateWithFlags: ") + hipGetErrorString(e));
     }
-    if (!s->cfork) HIP_TRY(hipEventCreateWithFlags(&s->cfork, hipEventDisableTiming));
+    s->cstreams.push_back(st);
+    s->cjoin.push_back(ev);
   }
+  if (!s->cfork) HIP_TRY(hipEventCreateWithFlags(&s->cfork, hipEventDisableTiming));
   HIP_TRY(hipEventRecord(s->cfork, stream));
   for (size_t ci = 0; ci < nc; ++ci) {
     HIP_TRY(hipStreamWaitEvent(s->cstreams[ci], s->cfork, 0));
@@ -1102,7 +1189,7 @@ hhlb_status enqueue_steps(hhlb_solver *s, int64_t n_steps, hipStream_t stream, b
     HIP_TRY(hipEventRecord(s->cjoin[ci], s->cstreams[ci]));
   }
   for (size_t ci = 0; ci < nc; ++ci) HIP_TRY(hipStreamWaitEvent(stream, s->cjoin[ci], 0));
-  if (s->mixed() && (n_steps & 1)) s->par ^= 1;
+  if (n_steps & 1) s->par ^= 1;
   return HHLB_OK;
 }
 
@@ -1135,16 +1222,14 @@ hhlb_status run_steps(hhlb_solver *s, int64_t n_steps) {
   }
   // graph replay on an internal stream, ordered after the caller's stream
   // and before whatever the caller enqueues next
-  if (!s->gstream) {
-    HIP_TRY(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
-  }
+  if (!s->ev_in) HIP_TRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
+  if (!s->ev_out) HIP_TRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
+  if (!s->gstream) HIP_TRY(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
   const int64_t K = s->tuning.graph_steps;
   const int64_t full = n_steps / K, rest = n_steps % K;
-  // the mixed form flips the state parity every step: one graph per
-  // starting parity, all captured before the first launch
-  for (int p = 0; p < (s->mixed() ? 2 : 1); ++p) {
+  // every step flips the state parity: one graph per starting parity, all
+  // captured before the first launch
+  for (int p = 0; p < 2; ++p) {
     const int par0 = s->par;
     s->par = p;
     hhlb_status st = HHLB_OK;
@@ -1157,11 +1242,11 @@ hhlb_status run_steps(hhlb_solver *s, int64_t n_steps) {
   HIP_TRY(hipStreamWaitEvent(s->gstream, s->ev_in, 0));
   for (int64_t r = 0; r < full; ++r) {
     HIP_TRY(hipGraphLaunch(s->gexec_k[s->par], s->gstream));
-    if (s->mixed() && (K & 1)) s->par ^= 1;
+    if (K & 1) s->par ^= 1;
   }
   for (int64_t r = 0; r < rest; ++r) {
     HIP_TRY(hipGraphLaunch(s->gexec_1[s->par], s->gstream));
-    if (s->mixed()) s->par ^= 1;
+    s->par ^= 1;
   }
   HIP_TRY(hipEventRecord(s->ev_out, s->gstream));
   HIP_TRY(hipStreamWaitEvent(s->stream, s->ev_out, 0));
@@ -1201,13 +1286,15 @@ extern "C" hhlb_status hhlb_set_graph_steps(hhlb_solver *s, int32_t steps_per_gr
 extern "C" hhlb_status hhlb_set_tuning(hhlb_solver *s, const hhlb_tuning *t) {
   if (!s || !t) return fail(HHLB_E_ARG, "null argument");
   if (t->graph_steps < 0 || (t->class_streams != 0 && t->class_streams != 1) || (t->xcd_map != 0 && t->xcd_map != 1) ||
-      (t->waves_per_window != 2 && t->waves_per_window != 4))
-    return fail(HHLB_E_ARG, "graph_steps >= 0, class_streams and xcd_map 0 or 1, waves_per_window 2 or 4");
+      (t->waves_per_window != 2 && t->waves_per_window != 4) || (t->step_fusion != 0 && t->step_fusion != 1))
+    return fail(HHLB_E_ARG,
+                "graph_steps >= 0, class_streams, xcd_map and step_fusion 0 or 1, waves_per_window 2 or 4");
   s->drop_graphs();
   s->tuning.graph_steps = t->graph_steps;
   s->tuning.class_streams = t->class_streams;
   s->tuning.xcd_map = t->xcd_map;
   s->tuning.waves_per_window = t->waves_per_window;
+  s->tuning.step_fusion = t->step_fusion;
   return HHLB_OK;
 }
 
@@ -1223,22 +1310,28 @@ extern "C" hhlb_status hhlb_autotune(hhlb_solver *s, int32_t trial_steps, hhlb_t
   hhlb_status st = check_flag(s);
   if (st) return st;
   const bool multi = s->classes.size() > 1;
-  bool has4 = false;
-  for (auto &mc : s->classes) has4 = has4 || mc.launch4 != nullptr;
+  bool has4 = false, hasf = false;
+  for (auto &mc : s->classes) {
+    has4 = has4 || mc.launch4 != nullptr;
+    hasf = hasf || mc.fused != nullptr;
+  }
   std::vector<hhlb_tuning> cands;
-  for (int wpw : {2, 4})
-    for (int gs : {0, 16})
-      for (int cs : {0, 1})
-        for (int xm : {1, 0}) {
-          if (cs && (!multi || gs > 0)) continue;   // class streams apply to direct launches
-          if (wpw == 4 && !has4) continue;
-          hhlb_tuning t{};
-          t.graph_steps = gs;
-          t.class_streams = cs;
-          t.xcd_map = xm;
-          t.waves_per_window = wpw;
-          cands.push_back(t);
-        }
+  for (int sf : {0, 1})
+    for (int wpw : {2, 4})
+      for (int gs : {0, 16})
+        for (int cs : {0, 1})
+          for (int xm : {1, 0}) {
+            if (cs && (!multi || gs > 0)) continue;   // class streams apply to direct launches
+            if (wpw == 4 && !has4) continue;
+            if (sf && !hasf) continue;
+            hhlb_tuning t{};
+            t.graph_steps = gs;
+            t.class_streams = cs;
+            t.xcd_map = xm;
+            t.waves_per_window = wpw;
+            t.step_fusion = sf;
+            cands.push_back(t);
+          }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -1308,18 +1401,18 @@ hhlb_status hhlb_diagnostics(hhlb_solver *s, double *n_wall_dev, double *mass_de
     HIP_TRY(hipMemcpyAsync(n_wall_dev, s->ws + s->o_nwall, sizeof(double) * 2 * n_ch, hipMemcpyDeviceToDevice,
                            s->stream));
   if (residual_dev) {
-    // one forward-Euler stage from the current state into the B copies; the
+    // one forward-Euler stage from the current state into the C copies; the
     // state (A) and the wall densities are left untouched
     if (s->mixed()) {
-      enqueue_stage(s, 0, nullptr, nullptr, s->fB, s->cB, 0.0, 1.0, s->stream);
+      enqueue_stage(s, 0, nullptr, nullptr, s->fC, s->cC, 0.0, 1.0, s->stream);
       hipLaunchKernelGGL(residual_kernel<float>, dim3(n_ch), dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans,
-                         a.ch_V, a.n_ch, a.scaled, 1, (const float *)s->fA(), (const float *)s->fB,
-                         (const float *)s->cA(), (const float *)s->cB, hc, residual_dev);
+                         a.ch_V, a.n_ch, a.scaled, 1, (const float *)s->fA(), (const float *)s->fC,
+                         (const float *)s->cA(), (const float *)s->cC, hc, residual_dev);
     } else {
-      enqueue_stage(s, 0, s->fA(), s->cA(), s->fB, s->cB, 0.0, 1.0, s->stream);
+      enqueue_stage(s, 0, s->fA(), s->cA(), s->fC, s->cC, 0.0, 1.0, s->stream);
       hipLaunchKernelGGL(residual_kernel<double>, dim3(n_ch), dim3(256), 0, s->stream, a.tbs, a.ch_class, a.chans,
-                         a.ch_V, a.n_ch, a.scaled, 0, (const double *)s->fA(), (const double *)s->fB,
-                         (const double *)s->cA(), (const double *)s->cB, hc, residual_dev);
+                         a.ch_V, a.n_ch, a.scaled, 0, (const double *)s->fA(), (const double *)s->fC,
+                         (const double *)s->cA(), (const double *)s->cC, hc, residual_dev);
     }
     HIP_TRY(hipGetLastError());
   }
@@ -1360,6 +1453,28 @@ hhlb_status hhlb_launch_info(const hhlb_solver *s, int32_t *launches_per_stage, 
     for (auto &mc : s->classes) t += (int64_t)mc.windows.size();
     *windows_total = t;
   }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_equilibrium_ladder(const hhlb_solver *s, int32_t channel, int32_t *counts, double *reach) {
+  if (!s || !counts || !reach) return fail(HHLB_E_ARG, "null argument");
+  if (channel < 0 || channel >= (int32_t)s->ch.size()) return fail(HHLB_E_ARG, "channel out of range");
+  const ModelClass &mc = s->classes[s->ch_class[channel]];
+  if (!hhlb::half_range(mc.quad)) return fail(HHLB_E_UNSUPPORTED, "the full-range equilibrium has no ladder");
+  for (int j = 0; j < hhlb::kLadder; ++j) {
+    counts[j] = mc.large ? ((const hhlb::DevLarge *)mc.lblob.data())->lad_n[j] : mc.dev.lad_n[j];
+    reach[j] = mc.large ? ((const hhlb::DevLarge *)mc.lblob.data())->lad_y[j] : mc.dev.lad_y[j];
+  }
+  return HHLB_OK;
+}
+
+hhlb_status hhlb_wide_equilibrium_count(const hhlb_solver *s, int64_t *count) {
+  if (!s || !count) return fail(HHLB_E_ARG, "null argument");
+  if (!s->ws) return fail(HHLB_E_STATE, "no workspace bound");
+  unsigned long long c = 0;
+  HIP_TRY(hipMemcpyAsync(&c, s->ws + s->o_wide, sizeof c, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  *count = (int64_t)c;
   return HHLB_OK;
 }
 

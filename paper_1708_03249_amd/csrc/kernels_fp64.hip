@@ -1,4 +1,6 @@
-// FP64 stage kernels: half-range (two waves per window) and full-range.
+// FP64 stage kernels: half-range (two waves per window) and full-range; the
+// fused-step kernel of the half-range model.
+#include "fused_kernels.hpp"
 #include "launch.hpp"
 
 namespace hhlb {
@@ -19,6 +21,12 @@ void launch_quarter(const StageArgs &a, hipStream_t s) {
                      a.inv_dx, a.gw, (const double *)a.in_f, (const double *)a.in_c);
 }
 
+template <int Q, int NF, int ADV>
+void launch_fused(const StageArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((fused_kernel_half<Q, NF, ADV>), dim3(a.nwin), dim3(128), 0, s, a, a.tb, a.chans, a.wins,
+                     a.inv_dx, a.gw, (const double *)a.in_f, (const double *)a.in_c);
+}
+
 template <int QUAD, int Q>
 void add(LaunchMap &m) {
   m[{QUAD, Q, 1, 0, 0, 2}] = launch_stage<QUAD, Q, 1, 0>;
@@ -28,6 +36,12 @@ void add(LaunchMap &m) {
   if constexpr (QUAD == 0) {   // four waves per window: f and chi, half range
     m[{QUAD, Q, 2, 0, 0, 4}] = launch_quarter<Q, 0>;
     m[{QUAD, Q, 2, 1, 0, 4}] = launch_quarter<Q, 1>;
+  }
+  if constexpr (QUAD == 0 && Q <= kQmaxFused) {   // one launch per RK-3 step
+    m[{QUAD, Q, 1, 0, 0, 1}] = launch_fused<Q, 1, 0>;
+    m[{QUAD, Q, 1, 1, 0, 1}] = launch_fused<Q, 1, 1>;
+    m[{QUAD, Q, 2, 0, 0, 1}] = launch_fused<Q, 2, 0>;
+    m[{QUAD, Q, 2, 1, 0, 1}] = launch_fused<Q, 2, 1>;
   }
 }
 

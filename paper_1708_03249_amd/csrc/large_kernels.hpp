@@ -1,7 +1,7 @@
 // Node-parallel FP64 stage for large velocity sets, equilibrium order
 // N <= 20: the half-range model with 17 <= Q <= 256 nodes per half and the
 // full-range model with 18 <= Q <= 512 nodes, the paper's HHLB(20;Q) and
-// HLB(20;Q) models of the ballistic study (Sec. VI.D).  The nodes of a half
+// HLB(20;Q) models of the ballistic study (Sec. V.E).  The nodes of a half
 // no longer fit a lane's registers, so one stage runs as two kernels:
 //   large_cell_kernel: one wave per cell, lanes over nodes and then over
 //     quadrature points: the moments (Eq. fmoms), 1/tau, the rank-1 force
@@ -56,6 +56,7 @@ struct LargeArgs {
   double *cell;                   // cell-phase output, kCellStride per cell
   double *lnw;                    // wall densities of this stage, 2 per channel
   double *nwall;                  // diagnostics copy (written in stage 2)
+  unsigned long long *wide;       // cells whose equilibrium needed several correction panels
   int32_t nfun;
   int32_t xcd_map;                // 1: the blocks of a window run on one XCD
 };
@@ -75,9 +76,10 @@ __device__ __forceinline__ double seg_sum(double x) {
 // collected by segment sums; for the full range the closed-form recurrence
 // of Sec. IV.A.3.  Called by every lane of the wave; W >= 16 holds the main
 // rule (at most 11 points for N <= 20) and the largest correction (16).
-// NM bounds the order N (the register arrays' size).
+// NM bounds the order N (the register arrays' size).  Returns the number of
+// correction panels used (more than one beyond the ladder's calibrated range).
 template <int W = 64, int NM = kNmaxLarge>
-__device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double T, int lane,
+__device__ __forceinline__ int axis_coeffs(const DevLarge *tl, double u, double T, int lane,
                                             double (&Gp)[NM + 1], double (&Gm)[NM + 1]) {
   const int N = tl->N;
 #pragma unroll
@@ -95,7 +97,7 @@ __device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double
       if (l + 1 <= N) Gp[l + 1] = (ub * Gp[l] + tl->sq[l] * aa * Gp[l - 1]) / tl->sq[l + 1];
 #pragma unroll
     for (int l = 0; l <= NM; ++l) Gm[l] = (l & 1) ? -Gp[l] : Gp[l];
-    return;
+    return 1;
   }
   const double sT = sqrt(T), s = sT * tl->inv_p0, y0 = -u / sT;
   auto accum = [&](double (&G)[NM + 1], double x, double wt) {
@@ -117,14 +119,20 @@ __device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double
     accum(Gm, -u * tl->inv_p0 + s * tl->zm[lane], tl->wm[lane]);
   }
   const double ymax = fabs(y0);
+  int P = 1;
   if (ymax > 0.0) {
     int li = kLadder - 1;
     for (int j = 1; j < kLadder; ++j)
       if (tl->lad_y[j] >= ymax) { li = j; break; }
     const int nc = tl->lad_n[li], o = tl->lad_off[li];
-    if (lane < nc) {   // nc <= 16 (the largest count of the ladder)
-      const double t = tl->ltau[o + lane], yt = y0 * t;
-      const double e = y0 * tl->llamw[o + lane] * exp(-0.5 * yt * yt);
+    // beyond the top count's calibrated range: equal panels of the top count
+    if (li == kLadder - 1) P = correction_panels(ymax, tl->lad_y[kLadder - 1]);
+    const double iP = 1.0 / P;   // exactly 1 for one panel
+    // nc <= 16 <= W: the segment's lanes take the points panel by panel
+    for (int q = lane; q < P * nc; q += W) {
+      const int p = q / nc, j = q - p * nc;
+      const double t = (p + tl->ltau[o + j]) * iP, yt = y0 * t;
+      const double e = y0 * (tl->llamw[o + j] * iP) * exp(-0.5 * yt * yt);
       accum(Gp, u * tl->inv_p0 * (1.0 - t), -e);
       accum(Gm, -u * tl->inv_p0 * (1.0 - t), e);
     }
@@ -136,6 +144,7 @@ __device__ __forceinline__ void axis_coeffs(const DevLarge *tl, double u, double
       Gm[l] = seg_sum<W>(Gm[l]);
     }
   }
+  return P;
 }
 
 // Cell phase: a 1-D grid of nwin x (kCellGroups + 1) blocks; block b maps to
@@ -200,7 +209,10 @@ __global__ __launch_bounds__(256) void large_cell_kernel(LargeArgs A) {
     double Gp[kNmaxLarge + 1], Gm[kNmaxLarge + 1];
 #pragma unroll
     for (int l = 0; l <= kNmaxLarge; ++l) Gp[l] = Gm[l] = 0.0;
-    if (C.inv_Kn != 0.0) axis_coeffs(tl, u, T, lane, Gp, Gm);
+    if (C.inv_Kn != 0.0) {
+      const int P = axis_coeffs(tl, u, T, lane, Gp, Gm);
+      if (P > 1 && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
+    }
     if (lane == 0) {
       double *out = A.cell + (int64_t)(C.cell_off + i) * kCellStride;
       out[0] = n;

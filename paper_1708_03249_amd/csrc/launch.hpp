@@ -12,7 +12,8 @@ namespace hhlb {
 
 using Launcher = void (*)(const StageArgs &, hipStream_t);
 // (quadrature kind, Q, functions (1 = f, 2 = f and chi), advection, precision,
-//  waves per window: 2 = the two-wave kernels, 4 = the four-wave FP64 kernel)
+//  shape: 2 = the two-wave stage kernels, 4 = the four-wave FP64 stage kernel,
+//  1 = the fused kernel of a whole RK-3 step)
 using LaunchKey = std::tuple<int, int, int, int, int, int>;
 using LaunchMap = std::map<LaunchKey, Launcher>;
 

@@ -168,6 +168,7 @@ typedef short bfx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 hfx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ short to_bf16(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+__device__ __forceinline__ float bf16_value(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
 // The value an operand has once rounded for the matrix cores.
 template <int PREC>
 __device__ __forceinline__ float operand_value(float x) {
@@ -198,29 +199,36 @@ struct ForceA<kPrecF32> {
     }
   }
 };
+// BF16 / FP16: the table as a high part v (the entry rounded to the operand
+// format) plus a low part lo (the remainder, exact in FP32, rounded again),
+// so that the products carry about twice the operand precision.
 template <>
 struct ForceA<kPrecBF16> {
-  bfx4 v;
+  bfx4 v, lo;
   template <int H>
   __device__ __forceinline__ void load(const float *Ks, int lane) {
     const int i = lane & 15;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int k = 4 * (lane >> 4) + t;
-      v[t] = to_bf16((i < H && k < H) ? Ks[(i < H ? i : 0) * H + (k < H ? k : 0)] : 0.0f);
+      const float x = (i < H && k < H) ? Ks[(i < H ? i : 0) * H + (k < H ? k : 0)] : 0.0f;
+      v[t] = to_bf16(x);
+      lo[t] = to_bf16(x - bf16_value(v[t]));
     }
   }
 };
 template <>
 struct ForceA<kPrecF16> {   // loaded from the row-scaled table Ks16
-  hfx4 v;
+  hfx4 v, lo;
   template <int H>
   __device__ __forceinline__ void load(const float *Ks, int lane) {
     const int i = lane & 15;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int k = 4 * (lane >> 4) + t;
-      v[t] = (_Float16)((i < H && k < H) ? Ks[(i < H ? i : 0) * H + (k < H ? k : 0)] : 0.0f);
+      const float x = (i < H && k < H) ? Ks[(i < H ? i : 0) * H + (k < H ? k : 0)] : 0.0f;
+      v[t] = (_Float16)x;
+      lo[t] = (_Float16)(x - (float)v[t]);
     }
   }
 };
@@ -255,16 +263,29 @@ __device__ __forceinline__ void mfma_force(const ForceA<PREC> &aM, const float X
         const int k = 4 * (lane >> 4) + t;
         bv[t] = k < H ? row[k < H ? k : 0] : 0.0f;
       }
+      // hi/lo split of both operands: Kh yh + Kh yl + Kl yh, the small
+      // products first (the dropped Kl yl is below 2^-16 of |K||y| in BF16,
+      // 2^-22 in FP16)
       if constexpr (PREC == kPrecBF16) {
-        bfx4 b;
+        bfx4 bh, bl;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) b[t] = to_bf16(bv[t]);
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aM.v, b, acc[cb], 0, 0, 0);
+        for (int t = 0; t < 4; ++t) {
+          bh[t] = to_bf16(bv[t]);
+          bl[t] = to_bf16(bv[t] - bf16_value(bh[t]));
+        }
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aM.lo, bh, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aM.v, bl, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aM.v, bh, acc[cb], 0, 0, 0);
       } else {
-        hfx4 b;
+        hfx4 bh, bl;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) b[t] = (_Float16)bv[t];
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(aM.v, b, acc[cb], 0, 0, 0);
+        for (int t = 0; t < 4; ++t) {
+          bh[t] = (_Float16)bv[t];
+          bl[t] = (_Float16)(bv[t] - (float)bh[t]);
+        }
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(aM.lo, bh, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(aM.v, bl, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(aM.v, bh, acc[cb], 0, 0, 0);
       }
     }
   }
@@ -458,12 +479,16 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
         if (tb->lad_y[j] >= ymax) { li = j; break; }
       const int nc = tb->lad_n[li], o = tb->lad_off[li];
       const double sgd = hw ? -1.0 : 1.0;
-      for (int j = 0; j < nc; ++j) {
-        const double t = tb->ltau[o + j];
-        const double yt = y0 * t;
-        const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
-        accum(ub * (1.0 - t), -sgd * e);
-      }
+      const int P = li == kLadder - 1 ? correction_panels(ymax, tb->lad_y[kLadder - 1]) : 1;
+      if (P > 1 && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
+      const double iP = 1.0 / P;   // exactly 1 for one panel
+      for (int p = 0; p < P; ++p)
+        for (int j = 0; j < nc; ++j) {
+          const double t = (p + tb->ltau[o + j]) * iP;
+          const double yt = y0 * t;
+          const double e = y0 * (tb->llamw[o + j] * iP) * exp(-0.5 * yt * yt);
+          accum(ub * (1.0 - t), -sgd * e);
+        }
     }
   }
 
@@ -532,11 +557,14 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
             isc = ldexpf(1.0f, e);
           }
           float ys[H];
-          float d = 0.0f;   // mass defect of the rounded block: sum_j crs_j yr_j
+          // mass defect of the split product Kh (yh + yl) + Kl yh:
+          // sum_j crs_j (yh_j + yl_j) + crs_lo_j yh_j (yh + yl is exact in FP32)
+          float d = 0.0f;
 #pragma unroll
           for (int j = 0; j < H; ++j) {
             ys[j] = y[j] * sc;
-            d += tb->crs[j] * operand_value<PREC>(ys[j]);
+            const float yh = operand_value<PREC>(ys[j]), yl = operand_value<PREC>(ys[j] - yh);
+            d = fmaf(tb->crs[j], yh + yl, fmaf(tb->crs_lo[j], yh, d));
           }
           mfma_force<PREC, H>(aK, ys, ky, Tw, lane);
           const float dc = d * isc * tb->iwh;

@@ -82,12 +82,15 @@ struct DevTables {
   float pf[2 * kQmaxDev];                 // p_k/m
   // reduced-precision force operands (BF16 / FP16 forms): the FP16 table is
   // Ks with row k scaled by rsc_k (a power of two, |row| <= 1) and irsc_k =
-  // 1/rsc_k; crs_j = sum_k w_k Kr_kj are the weighted column sums of the
-  // table exactly as the matrix cores see it (Kr), whose mass defect the
-  // kernel removes; iwh = 1 / sum over a half of w_k
+  // 1/rsc_k.  The matrix cores see the table as a high part Kh (the operand
+  // rounding of it) plus a low part Kl (the rounding of the remainder);
+  // crs_j = sum_k w_k Kh_kj and crs_lo_j = sum_k w_k Kl_kj are their weighted
+  // column sums exactly as rounded, whose mass defect the kernel removes;
+  // iwh = 1 / sum over a half of w_k
   float Ks16[kQmaxDev * kQmaxDev];
   float irsc[kQmaxDev];
   float crs[kQmaxDev];
+  float crs_lo[kQmaxDev];                 // the same sums for the table's low part (hi/lo split)
   float iwh;
 };
 
@@ -129,6 +132,9 @@ struct StageArgs {
   void *out_f, *out_c;
   double a_base, b_stage;    // out = a_base * y^n + b_stage * (y_s + dt L[y_s])
   double *nwall;             // 2 per channel (may be null)
+  // count of waves whose equilibrium needed more than one correction panel
+  // (|y0| beyond the calibrated range of the ladder; may be null)
+  unsigned long long *wide;
   // mixed form only: 16-bit correction words of y^n (read in the last stage)
   // and of y^{n+1} (written there)
   const int16_t *lo_in_f, *lo_in_c;
@@ -310,6 +316,20 @@ __device__ __forceinline__ int xcd_window(int b, int n) {
   const int q = n >> 3, r = n & 7;
   const int x = b & 7, pos = b >> 3;
   return x * q + (x < r ? x : r) + pos;
+}
+
+// Panels of the correction integral over [y0, 0] of the half-range
+// equilibrium (the change of variables of the host builder): one while the
+// largest |y0| of the wave lies within the range the ladder's top count was
+// calibrated for (ytop), else the number of equal panels of that integral
+// that keeps each one within it (a composite rule of the top count).  The
+// count is capped at kMaxPanels, which also covers non-finite |y0|.  A ladder
+// without a calibrated top count (ytop <= 0) keeps one panel.
+constexpr int kMaxPanels = 64;
+__device__ __forceinline__ int correction_panels(double ymax, double ytop) {
+  if (!(ytop > 0.0) || ymax <= ytop) return 1;
+  if (!(ymax < ytop * kMaxPanels)) return kMaxPanels;
+  return (int)ceil(ymax / ytop);
 }
 
 // Wall density of Eq. (nplus_def): n_w = -sum_in F_k / sum_out (p_k/m) g^w_k,
@@ -801,12 +821,16 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
       for (int j = 1; j < kLadder; ++j)
         if (tb->lad_y[j] >= ymax) { li = j; break; }
       const int nc = tb->lad_n[li], o = tb->lad_off[li];
-      for (int j = 0; j < nc; ++j) {
-        const double t = tb->ltau[o + j];
-        const double yt = y0 * t;
-        const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
-        accum(ub * (1.0 - t), -sg * e);
-      }
+      const int P = li == kLadder - 1 ? correction_panels(ymax, tb->lad_y[kLadder - 1]) : 1;
+      if (P > 1 && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
+      const double iP = 1.0 / P;   // exactly 1 for one panel
+      for (int p = 0; p < P; ++p)
+        for (int j = 0; j < nc; ++j) {
+          const double t = (p + tb->ltau[o + j]) * iP;
+          const double yt = y0 * t;
+          const double e = y0 * (tb->llamw[o + j] * iP) * exp(-0.5 * yt * yt);
+          accum(ub * (1.0 - t), -sg * e);
+        }
     }
   }
 
@@ -1103,12 +1127,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HHLB_QUARTE
       for (int j = 1; j < kLadder; ++j)
         if (tb->lad_y[j] >= ymax) { li = j; break; }
       const int nc = tb->lad_n[li], o = tb->lad_off[li];
-      for (int j = 0; j < nc; ++j) {
-        const double t = tb->ltau[o + j];
-        const double yt = y0 * t;
-        const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
-        accum(ub * (1.0 - t), -sg * e);
-      }
+      const int P = li == kLadder - 1 ? correction_panels(ymax, tb->lad_y[kLadder - 1]) : 1;
+      if (P > 1 && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
+      const double iP = 1.0 / P;   // exactly 1 for one panel
+      for (int p = 0; p < P; ++p)
+        for (int j = 0; j < nc; ++j) {
+          const double t = (p + tb->ltau[o + j]) * iP;
+          const double yt = y0 * t;
+          const double e = y0 * (tb->llamw[o + j] * iP) * exp(-0.5 * yt * yt);
+          accum(ub * (1.0 - t), -sg * e);
+        }
     }
   }
 

@@ -54,11 +54,35 @@ def run_gpu(channels, states, nsteps, precision=0, tuning=None):
     return res
 
 
-def run_oracle(channels, states, nsteps, dts, which=None, workers=8):
+def oracle_dt(ch) -> float:
+    """The oracle's own time step of a channel: the given dt, or for a CFL
+    request (dt < 0) min(|dt| min dx / max |p|, Kn/2) from the oracle's grid
+    and nodes."""
+    oc = to_oracle(ch)
+    return float(ch.dt) if ch.dt > 0 else O.cfl_dt(oc, -ch.dt)
+
+
+def check_dt(channels, gpu_dt, which=None):
+    """The library's resolved time steps (hhlb_time_steps) against the
+    oracle's own, within two ulps; returns the oracle's."""
     which = range(len(channels)) if which is None else which
+    out = {}
+    for c in which:
+        d = oracle_dt(channels[c])
+        assert abs(gpu_dt[c] - d) <= 4.5e-16 * d, (c, gpu_dt[c], d)
+        out[c] = d
+    return out
+
+
+def run_oracle(channels, states, nsteps, gpu_dt=None, which=None, workers=8):
+    """The oracle on the same inputs, with its own time step (checked
+    against the library's resolved one when gpu_dt is given)."""
+    which = list(range(len(channels)) if which is None else which)
+    dts = check_dt(channels, gpu_dt, which) if gpu_dt is not None else \
+        {c: oracle_dt(channels[c]) for c in which}
 
     def one(c):
-        oc = to_oracle(channels[c], dt=float(dts[c]))
+        oc = to_oracle(channels[c], dt=dts[c])
         f, chi, nw = O.run(oc, nsteps, states[c][0], states[c][1])
         n, u, T = O.moments(oc, f, chi)
         return c, dict(f=f, chi=chi, nw=nw, n=n, u=u, T=T)

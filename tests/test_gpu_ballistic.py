@@ -1,4 +1,4 @@
-"""Ballistic validation (Sec. VI.D) on the paper's grid (Nx = 24, stretching
+"""Ballistic validation (Sec. V.E) on the paper's grid (Nx = 24, stretching
 A = 0.99, dt = 1e-4, Kn = inf, the 1-D gas), from the equilibrium at rest to
 the steady state, against the closed forms Eqs. (bal_n) and (bal_temp) and
 the paper's convergence criterion Eq. (epsmax), eps_max < 1 %, for every
@@ -8,8 +8,8 @@ along x, so the solver's acceleration is g = -g_p.  The eight cases run as
 one batch of channels.
   - HHLB(20;200) meets the criterion in every case.
   - HLB(20;500), the full-range model at the paper's largest Q, does not:
-    the paper reports eps_max of about 25.9 % even at Q = 500 (Sec. VI.D,
-    repeated in Sec. VII).  Equal walls are the exception: there the
+    the paper reports eps_max of about 25.9 % even at Q = 500 (Sec. V.E,
+    repeated in Sec. VI).  Equal walls are the exception: there the
     full-range equilibrium is the exact barometric solution."""
 import math
 import os
@@ -98,7 +98,7 @@ def test_ballistic_steady_state_meets_paper_criterion():
     assert e0 > 1.0
 
 
-# eps_max the paper reports for HLB(20;500) (Sec. VI.D and Sec. VII); the
+# eps_max the paper reports for HLB(20;500) (Sec. V.E and Sec. VI); the
 # text attaches the failing full-range runs to g_p = 0.1, Delta T = -0.4
 PAPER_HLB500_EPS = 0.259
 

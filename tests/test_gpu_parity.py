@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from gpu_common import compare, initial_states, run_gpu, run_oracle  # noqa: E402
+from gpu_common import compare, initial_states, oracle_dt, run_gpu, run_oracle  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -156,7 +156,7 @@ def test_full_range_large_q_node_parallel():
 
 def test_full_range_hlb_20_500_ballistic_setup():
     """HLB(20;500), the paper's largest full-range model of the ballistic
-    study (Sec. VI.D), on its grid: Nx = 24, A = 0.99, Kn = inf, g_p = 1,
+    study (Sec. V.E), on its grid: Nx = 24, A = 0.99, Kn = inf, g_p = 1,
     T_left = 1.4, T_right = 0.6, dt = 1e-4; 30 steps against the oracle from
     the equilibrium at rest (smooth in p, as for HHLB(20;200))."""
     h = H()
@@ -183,7 +183,7 @@ def test_large_q_limits_minimum_grid():
 
 
 def test_ballistic_hhlb_20_200_setup():
-    """The paper's ballistic configuration (Sec. VI.D): HHLB(20;200), V = 400,
+    """The paper's ballistic configuration (Sec. V.E): HHLB(20;200), V = 400,
     Nx = 24, A = 0.99, Kn = inf, g = 0.1, T_left = 1.4, T_right = 0.6,
     dt = 1e-4, the 1-D gas (no chi); 40 steps against the oracle from the
     equilibrium at rest.  The start is smooth in p on purpose: at V = 400 the
@@ -295,29 +295,46 @@ def test_small_channel_20000_steps_golden():
 
 
 def test_bench_size_sampled_channels():
-    """The benchmark configuration at full size (256 channels x Nx = 16384,
-    HHLB(15;16), WENO-5, f and chi, stretched A = 0.9, CFL 0.5, graph
-    replay): 3 steps of the whole batch on the GPU; channels 0, 137 and 255
-    (first, interior, last) against the oracle."""
+    """The benchmark configuration at full size and in its launch shape (256
+    channels x Nx = 16384, HHLB(15;16), WENO-5, f and chi, stretched A = 0.9,
+    CFL 0.5, direct launches) from the start the benchmark times: the
+    equilibrium (1, 0, 1) times the seeded smooth modulation of every
+    population row (the seeds of bench.init_developed), built here from the
+    oracle's equilibrium.  20 steps of the whole batch on the GPU; channels
+    0, 85, 170 and 255 against the oracle, which resolves its own time step
+    (checked against the library's)."""
     import torch
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
+    import oracle as O
+    from gpu_common import to_oracle
+    from paper_1708_03249_amd.inputs import smooth_modulation
     chans = bench.workload()
     h = H()
     s = h.Solver(chans)
-    s.init_equilibrium(1.0, 0.0, 1.0)
-    print("[parity] bench size, 256 x 16384, 3 steps", flush=True)
-    s.step(3)
+    which, nsteps = (0, 85, 170, 255), 20
+    print(f"[parity] bench size, 256 x 16384, developed start, {nsteps} steps", flush=True)
+    feq, _ = O.initial_state(to_oracle(chans[0]))     # every channel starts from the same (1, 0, 1)
+    col = torch.from_numpy(np.ascontiguousarray(feq[:, :1])).cuda()
+    f = torch.empty(s.total, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(f)
+    V, Nx = chans[0].V, chans[0].Nx
+    for k in range(len(chans)):
+        o0, o1 = int(s.offsets[k]), int(s.offsets[k + 1])
+        mf = torch.from_numpy(smooth_modulation(2 * k, V, Nx, 0.05)).cuda()
+        mc = torch.from_numpy(smooth_modulation(2 * k + 1, V, Nx, 0.05)).cuda()
+        f[o0:o1] = (col * mf).reshape(-1)
+        c[o0:o1] = (col * mc).reshape(-1)     # chi = (Dt/2) T0 f_eq = f_eq at T0 = 1, Dt = 2
+    s.set_state(f, c)
+    del f, c
+    s.step(nsteps)
     f, c = s.get_state()
     n, u, T = s.moments()
     nw, mass, bad = s.diagnostics()
     torch.cuda.synchronize()
     assert int(bad.item()) == 0
-    which = (0, 137, 255)
-    gpu = dict(offsets=np.zeros(len(chans) + 1, dtype=np.int64), cells=np.zeros(len(chans) + 1,
-               dtype=np.int64), f=[], chi=[], n=[], u=[], T=[], nw=np.zeros((len(chans), 2)))
-    # pack the sampled channels contiguously so compare() can index them
     sub = [chans[w] for w in which]
+    gpu = dict(f=[], chi=[], n=[], u=[], T=[])
     off, cel = [0], [0]
     for w, ch in zip(which, sub):
         gpu["f"].append(s.channel_view(f, w).cpu().numpy().ravel())
@@ -334,14 +351,14 @@ def test_bench_size_sampled_channels():
     gpu["offsets"], gpu["cells"] = np.array(off), np.array(cel)
     dts = [s.dt[w] for w in which]
     s.close()
-    from gpu_common import to_oracle
-    import oracle as O
+    del f, c, n, u, T
+    torch.cuda.empty_cache()
     states = []
-    for ch in sub:
-        fo, co = O.initial_state(to_oracle(ch))
-        states.append((fo, co))
-    ref = run_oracle(sub, states, 3, dts)
-    compare(sub, gpu, ref, tol=TOL, what="bench size")
+    for w in which:
+        states.append((np.ascontiguousarray(feq * smooth_modulation(2 * w, V, Nx, 0.05)),
+                       np.ascontiguousarray(feq * smooth_modulation(2 * w + 1, V, Nx, 0.05))))
+    ref = run_oracle(sub, states, nsteps, dts, workers=4)
+    compare(sub, gpu, ref, tol=TOL, what="bench size, developed start")
 
 
 def _batch_sample(n=9, steps_nx=None):
@@ -393,8 +410,9 @@ def test_launch_configurations_bit_identical(form):
         assert np.array_equal(outs[0][1], outs[k][1]), configs[k]
     # autotune: direct launches x {one stream, class streams} x 2 mappings and
     # 16-step graphs x 2 mappings, for 2 and (FP64 form) 4 waves per window,
-    # (trial + 1) steps each; the four-wave kernel rounds differently from the
-    # two-wave one, so the comparison solver replays the same configurations
+    # and (FP64 form) with and without step fusion, (trial + 1) steps each;
+    # the four-wave and fused kernels round differently from the two-wave
+    # one, so the comparison solver replays the same configurations
     s = h.Solver(chans, precision=prec)
     s.set_state(f0, c0)
     best = s.autotune(trial_steps=2)
@@ -403,10 +421,12 @@ def test_launch_configurations_bit_identical(form):
     f, c = s.get_state()
     r = h.Solver(chans, precision=prec)
     r.set_state(f0, c0)
-    for wpw in ((2, 4) if form == "fp64" else (2,)):
-        r.set_tuning(waves_per_window=wpw)
-        r.step(6 * 3)
-    r.set_tuning(**{k: best[k] for k in ("graph_steps", "class_streams", "xcd_map", "waves_per_window")})
+    for sf in ((0, 1) if form == "fp64" else (0,)):
+        for wpw in ((2, 4) if form == "fp64" else (2,)):
+            r.set_tuning(waves_per_window=wpw, step_fusion=sf)
+            r.step(6 * 3)
+    r.set_tuning(**{k: best[k] for k in ("graph_steps", "class_streams", "xcd_map", "waves_per_window",
+                                         "step_fusion")})
     r.step(1)
     fr, cr = r.get_state()
     torch.cuda.synchronize()
@@ -439,7 +459,7 @@ def test_residual_against_oracle_rhs(form, tol):
     for k, ch in enumerate(chans):
         fk = s.channel_view(torch.from_numpy(f), k).numpy()
         ck = s.channel_view(torch.from_numpy(c), k).numpy()
-        Lf, Lc, _ = O.rhs(to_oracle(ch, dt=float(s.dt[k])), fk, ck)
+        Lf, Lc, _ = O.rhs(to_oracle(ch, dt=oracle_dt(ch)), fk, ck)
         r = max(np.abs(Lf).max() / np.abs(fk).max(), np.abs(Lc).max() / np.abs(ck).max())
         assert abs(res[k] / r - 1) < tol, (form, k, res[k], r)
     s.close()
@@ -464,3 +484,44 @@ def test_four_waves_per_window_against_oracle():
             h.Channel(quad=h.HALF_HERMITE, Q=4, Nx=117, adv=h.UPWIND3, transverse_dof=0, Kn=0.2,
                       g=-0.2, T_right=1.1, dt=-0.4)]
     _check(edge, 80, perturb=0.03, seed=5, what="edge batch, 4 waves", tuning=t4)
+
+
+FUSED = dict(step_fusion=1)
+
+
+def test_step_fusion_small_channel_and_edges():
+    """The fused-step kernel (three RK-3 stages per launch, 9-cell halos)
+    against the oracle: the small channel (HHLB(3;4), Nx = 64, upwind-3:
+    a left-wall window and a right-wall window), Nx = 8 (both walls in one
+    window), Q = 1 and 2, no chi, collisionless, positive g, p0 != 1."""
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=4, Nx=64, adv=h.UPWIND3, transverse_dof=2, Kn=0.1,
+                       g=-0.1, dt=5e-4),
+             h.Channel(quad=h.HALF_HERMITE, Q=6, N=3, Nx=8, adv=h.WENO5, transverse_dof=0,
+                       Kn=math.inf, g=0.3, p0=1.2, T_left=1.2, T_right=0.8, dt=2e-4),
+             h.Channel(quad=h.HALF_HERMITE, Q=1, N=0, Nx=59, adv=h.UPWIND3, transverse_dof=0,
+                       Kn=0.3, g=-0.2, dt=1e-3),
+             h.Channel(quad=h.HALF_HERMITE, Q=2, Nx=116, adv=h.WENO5, transverse_dof=2, Kn=0.05,
+                       g=-0.7, T_right=1.3, dt=-0.4)]
+    _check(chans, 60, perturb=0.03, seed=17, what="fused: small and edge", tuning=FUSED)
+
+
+@pytest.mark.parametrize("Q", [4, 8, 12, 16])
+def test_step_fusion_stretched_weno5(Q):
+    """Fused steps on stretched WENO-5 channels with unequal walls at three
+    Kn (interior windows with 9-cell halos on both sides: Nx = 333 gives a
+    left-wall window, six interior ones and a ragged right-wall window),
+    from a perturbed start."""
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=Q, Nx=333, adv=h.WENO5, stretch_A=0.9,
+                       T_left=1.0, T_right=2.0, g=-0.5, Kn=kn, dt=-0.5) for kn in (0.01, 0.1, 1.0)]
+    _check(chans, 30, perturb=0.02, seed=19, what=f"fused: stretched Q={Q}", tuning=FUSED)
+
+
+def test_step_fusion_batched_sample_with_graphs():
+    """The first channels of the batched workload (uneven Nx, Q in {4, 8, 12},
+    Kn down to 1e-3) with fused steps under graph replay (two graphs per
+    starting copy of the ping-pong pair), against the oracle."""
+    chans = _batch_sample(9)
+    _check(chans, 25, perturb=0.02, seed=23, what="fused: batched sample, graphs",
+           tuning=dict(step_fusion=1, graph_steps=4))

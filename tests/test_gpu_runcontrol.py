@@ -1,0 +1,168 @@
+"""Run control through the C ABI: the equilibrium beyond the correction
+ladder's calibrated range (composite rule, counted), the non-finite state
+guard (HHLB_E_NUMERIC), an unstable time step caught by it, and a bitwise
+checkpoint round trip (get_state / set_state into a fresh solver)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_common import compare, initial_states, run_oracle  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1708_03249_amd as H
+    H.lib()
+
+
+def _H():
+    import paper_1708_03249_amd as H
+    return H
+
+
+def _solver_from(chans, states, precision=0):
+    import torch
+    H = _H()
+    s = H.Solver(chans, precision=precision)
+    f = torch.from_numpy(np.concatenate([st[0].ravel() for st in states])).cuda()
+    c = torch.from_numpy(np.concatenate([st[1].ravel() for st in states])).cuda()
+    s.set_state(f, c if s.has_chi else None)
+    return s
+
+
+def _collect(s):
+    import torch
+    f, c = s.get_state()
+    n, u, T = s.moments()
+    nw, mass, bad = s.diagnostics()
+    torch.cuda.synchronize()
+    return dict(f=f.cpu().numpy(), chi=c.cpu().numpy(), n=n.cpu().numpy(), u=u.cpu().numpy(),
+                T=T.cpu().numpy(), nw=nw.cpu().numpy(), mass=mass.cpu().numpy(),
+                bad=int(bad.cpu().item()), offsets=s.offsets, cells=s.cells, dt=s.dt.copy())
+
+
+@pytest.mark.parametrize("u0", [2.2, -3.1])
+def test_wide_equilibrium_against_oracle(u0):
+    """A supersonic start, |u|/sqrt(T) = 2.2 and 3.1, beyond the |y0| <= 1 the
+    correction ladder was calibrated for: the kernels split the correction
+    integral into panels.  Q = 4 upwind-3, Q = 8 and Q = 16 (matrix-core
+    path) WENO-5, and Q = 40 (node-parallel path), 6 steps against the
+    oracle's definition-based equilibrium; the evaluations are counted."""
+    H = _H()
+    chans = [H.Channel(quad=H.HALF_HERMITE, Q=4, Nx=70, adv=H.UPWIND3, Kn=0.05, g=-0.3, dt=-0.4),
+             H.Channel(quad=H.HALF_HERMITE, Q=8, Nx=130, adv=H.WENO5, stretch_A=0.8, Kn=0.02, g=-0.5,
+                       T_left=1.0, T_right=1.4, dt=-0.4),
+             H.Channel(quad=H.HALF_HERMITE, Q=16, Nx=64, adv=H.WENO5, Kn=0.1, g=-0.2, dt=-0.4)]
+    if u0 > 0:
+        chans.append(H.Channel(quad=H.HALF_HERMITE, Q=40, N=20, Nx=40, adv=H.WENO5, Kn=0.1, g=-0.1,
+                               dt=2e-4))
+    print(f"[runcontrol] wide equilibrium u0 = {u0}: {len(chans)} channels, 6 steps", flush=True)
+    states = initial_states(chans, u0=u0, T0=1.0)
+    s = _solver_from(chans, states)
+    s.step(6)
+    gpu = _collect(s)
+    wide = s.wide_equilibrium_count()
+    s.close()
+    assert gpu["bad"] == 0
+    assert wide > 0
+    ref = run_oracle(chans, states, 6, gpu["dt"])
+    compare(chans, gpu, ref, tol=TOL, what=f"wide equilibrium u0={u0}")
+
+
+def test_subsonic_state_keeps_one_panel():
+    """At |u|/sqrt(T) <= 0.3 every evaluation stays within the calibrated
+    range: the count stays zero."""
+    H = _H()
+    ch = H.Channel(quad=H.HALF_HERMITE, Q=8, Nx=100, adv=H.WENO5, Kn=0.05, g=-0.5, T_left=1.0,
+                   T_right=1.5, dt=-0.5)
+    s = _solver_from([ch], initial_states([ch], u0=0.3, seed=3, perturb=0.02))
+    s.step(20)
+    assert s.wide_equilibrium_count() == 0
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_nonfinite_state_is_reported_and_not_stepped(precision):
+    """A NaN population set through hhlb_set_state: hhlb_diagnostics counts
+    it, the next hhlb_step returns HHLB_E_NUMERIC and advances nothing (the
+    state read back equals the one set, bit for bit in FP64)."""
+    import torch
+    H = _H()
+    ch = H.Channel(quad=H.HALF_HERMITE, Q=4, Nx=64, adv=H.UPWIND3, Kn=0.1, g=-0.1, dt=5e-4)
+    (f, c), = initial_states([ch], seed=5, perturb=0.01)
+    f = f.copy()
+    f[3, 17] = np.nan
+    s = _solver_from([ch], [(f, c)], precision=precision)
+    before = _collect(s)
+    assert before["bad"] == 1
+    with pytest.raises(H.HHLBError) as e:
+        s.step(5)
+    assert e.value.status == -5
+    after = _collect(s)
+    torch.cuda.synchronize()
+    if precision == 0:
+        np.testing.assert_array_equal(after["f"], before["f"])
+        np.testing.assert_array_equal(after["chi"], before["chi"])
+    assert np.isnan(after["f"].reshape(ch.V, ch.Nx)[3, 17])
+    # the flag stays set while the state holds the NaN
+    with pytest.raises(H.HHLBError):
+        s.step(1)
+    s.close()
+
+
+def test_unstable_time_step_is_caught():
+    """A time step far above the stability limit (dt = 40 times the CFL 0.5
+    step) blows the state up; the next diagnostics finds the non-finite
+    populations and hhlb_step refuses to continue."""
+    H = _H()
+    ch = H.Channel(quad=H.HALF_HERMITE, Q=4, Nx=64, adv=H.WENO5, Kn=1.0, g=-0.5, dt=-20.0)
+    s = _solver_from([ch], initial_states([ch], seed=7, perturb=0.05))
+    s.step(200)
+    _, _, bad = s.diagnostics()
+    assert int(bad.item()) > 0
+    with pytest.raises(H.HHLBError) as e:
+        s.step(1)
+    assert e.value.status == -5
+    s.close()
+
+
+@pytest.mark.parametrize("graph", [0, 8])
+def test_checkpoint_round_trip_bitwise(graph):
+    """2N steps in one solver equal N steps, hhlb_get_state, a fresh solver,
+    hhlb_set_state and N more steps, bit for bit (FP64; also with graph
+    replay)."""
+    import torch
+    H = _H()
+    chans = [H.Channel(quad=H.HALF_HERMITE, Q=8, Nx=150, adv=H.WENO5, stretch_A=0.9, Kn=0.02, g=-0.5,
+                       T_left=1.0, T_right=1.5, dt=-0.5),
+             H.Channel(quad=H.FULL_HERMITE, Q=16, Nx=90, adv=H.WENO5, Kn=0.1, g=-0.3, dt=-0.5)]
+    states = initial_states(chans, seed=9, perturb=0.03)
+    a = _solver_from(chans, states)
+    a.set_graph_steps(graph)
+    a.step(40)
+    ref = _collect(a)
+    a.close()
+    b = _solver_from(chans, states)
+    b.set_graph_steps(graph)
+    b.step(20)
+    f, c = b.get_state()
+    torch.cuda.synchronize()
+    b.close()
+    d = _H().Solver(chans)
+    d.set_graph_steps(graph)
+    d.set_state(f, c)
+    d.step(20)
+    got = _collect(d)
+    d.close()
+    np.testing.assert_array_equal(got["f"], ref["f"])
+    np.testing.assert_array_equal(got["chi"], ref["chi"])

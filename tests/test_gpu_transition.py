@@ -1,4 +1,4 @@
-"""Transition-regime convergence sweep (Sec. VI.E) as one batched solver:
+"""Transition-regime convergence sweep (Sec. V.G) as one batched solver:
 the full-range HLB(N;Q) and half-range HHLB(N;Q) models against reference
 profiles from HHLB(20;200), on the ballistic grid (Nx = 24, A = 0.99,
 dt = 1e-4, the 1-D gas) with Delta T = -0.4 (T_+ = 1.4, T_- = 0.6), for

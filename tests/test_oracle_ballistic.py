@@ -1,4 +1,4 @@
-"""Pins of the closed-form ballistic solution (Sec. VI.C) that the ballistic
+"""Pins of the closed-form ballistic solution (Sec. V.D) that the ballistic
 validation compares against.  Each closed form is checked against what fixes
 it independently: the kinetic solution Eq. (f_bal) integrated over p at 40
 digits (density, temperature, mass flux, heat flux), the stationary

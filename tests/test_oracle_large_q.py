@@ -1,7 +1,7 @@
 """Pins of the oracle's large-Q half-range Gauss-Hermite construction (the
 three-term recurrence from a discretised Stieltjes procedure, Sturm
 bisection for the nodes, Eq. wk_half_gen for the weights), used above Q = 16
-and needed for the paper's HHLB(20;200) runs (Sec. VI.D).  Checked against
+and needed for the paper's HHLB(20;200) runs (Sec. V.E).  Checked against
 the monomial construction where both apply, and against what the weight
 fixes at any Q: exactness against the Gamma-function moments, the
 force-moment identity, mass conservation and the equilibrium's half-range

@@ -490,3 +490,43 @@ def test_barometric_profile_small_channel():
     assert np.max(np.abs(n / nref - 1)) < 2e-4
     assert np.max(np.abs(u)) < 2e-4
     assert np.max(np.abs(T - 1)) < 2e-4
+
+
+@pytest.mark.parametrize("Nx,A", [(64, 0.9), (513, 0.99), (24, 0.99), (512, 0.5)])
+def test_stretched_grid_faces(Nx, A):
+    """Sec. IV.C.2, Eqs. (x_eta) and (etai): the faces x(eta_{i +- 1/2}) of
+    Nx cells of equal eta-width on [-artanh A, artanh A].  Pinned without the
+    mapping itself: the end faces are the walls -L/2, +L/2 (tanh(artanh A) =
+    A); the grid is mirror-symmetric about x = 0; the cells are coarsest at
+    the centre and densest at the walls (the paper's stated purpose), widening
+    monotonically towards the centre; and, since dx/deta = L/(2A) sech^2 eta,
+    the width ratio wall/centre tends to 1 - A^2 as Nx grows (midpoint
+    widths, checked to O(deta^2))."""
+    L = 1.0
+    ch = O.Channel(Q=2, Nx=Nx, A=A, L=L)
+    xf, dx, xc = O.grid(ch)
+    assert xf[0] == pytest.approx(-L / 2, abs=2e-16) and xf[-1] == pytest.approx(L / 2, abs=2e-16)
+    np.testing.assert_allclose(xf, -xf[::-1], rtol=0, atol=4e-16)
+    np.testing.assert_allclose(dx, dx[::-1], rtol=4e-13, atol=0)
+    np.testing.assert_allclose(np.diff(xf), dx, rtol=1e-12, atol=0)
+    assert abs(dx.sum() - L) < 1e-14
+    half = dx[: (Nx + 1) // 2]
+    assert np.all(np.diff(half) > 0), "cells must widen from the wall towards the centre"
+    assert dx.argmin() in (0, Nx - 1)
+    deta = 2.0 / Nx * math.atanh(A)
+    centre = L / (2 * A) * deta            # dx at eta = 0 to O(deta^3)
+    wall = centre * (1 - A * A)            # dx at eta = +-artanh A to first order
+    # the wall cell's own midpoint sits deta/2 inside the wall: sech^2 there
+    eta_w = math.atanh(A) - deta / 2
+    assert dx[0] == pytest.approx(centre / math.cosh(eta_w) ** 2, rel=deta ** 2)
+    assert dx[0] / dx.max() == pytest.approx(1 - A * A, rel=3 * deta + deta ** 2 * 50)
+    assert wall > 0
+
+
+def test_uniform_grid_when_unstretched():
+    """A = 0: Nx equal cells of width L/Nx between the walls."""
+    for Nx, L in ((64, 1.0), (17, 2.5)):
+        xf, dx, xc = O.grid(O.Channel(Q=2, Nx=Nx, A=0.0, L=L))
+        np.testing.assert_allclose(dx, L / Nx, rtol=1e-14)
+        np.testing.assert_allclose(xc, 0.5 * (xf[1:] + xf[:-1]), atol=1e-15)
+        assert xf[0] == pytest.approx(-L / 2) and xf[-1] == pytest.approx(L / 2)
