@@ -66,13 +66,23 @@ def workload(n_ch=N_CH, nx=NX, quad=None):
 
 
 def bytes_per_node_update(form="fp64", nfun=2):
-    """Algorithmic HBM bytes of one RK-3 step with one kernel per stage.
-    FP64: stage 1 reads y^n and writes y1; stages 2 and 3 read the stage state
-    and y^n and write the next state: 8 passes of 8 bytes per function.
-    Mixed: stage 1 reads hi (4) and writes d1 (4); stage 2 reads hi and d1 and
-    writes d2; stage 3 reads hi, lo (2) and d2 and writes hi and lo: 36 bytes
-    per function."""
-    return nfun * (64 if form == "fp64" else 36)
+    """Algorithmic HBM bytes of one RK-3 step.  One kernel per stage, FP64:
+    stage 1 reads y^n and writes y1; stages 2 and 3 read the stage state and
+    y^n and write the next state: 8 passes of 8 bytes per function.  Mixed:
+    stage 1 reads hi (4) and writes d1 (4); stage 2 reads hi and d1 and writes
+    d2; stage 3 reads hi, lo (2) and d2 and writes hi and lo: 36 bytes per
+    function.  Fused FP64 step: y^n in, y^{n+1} out, 16 bytes per function
+    (the method's minimum)."""
+    return nfun * {"fp64": 64, "fp64_fused": 16}.get(form, 36)
+
+
+def form_precision(H, form):
+    """Arithmetic form of a bench form name (fp64_fused: FP64, fused steps)."""
+    return H.PRECISIONS["fp64" if form == "fp64_fused" else form]
+
+
+def form_tuning(form):
+    return {"step_fusion": 1} if form == "fp64_fused" else {}
 
 
 def batch_workload(n_ch=4096, seed=0):
@@ -110,24 +120,50 @@ def init_developed(s, torch, np, seed=0, amplitude=0.05):
     return mass0.clone()
 
 
+TUNING_KEYS = ("graph_steps", "class_streams", "xcd_map", "waves_per_window", "step_fusion")
+
+
+def tune_on_sample(H, torch, np, chans, form, trial_steps=10, stride=8):
+    """hhlb_autotune on every stride-th channel of the batch (the candidates
+    are timed on that sample); returns the chosen configuration."""
+    s = H.Solver(chans[::stride], precision=H.PRECISIONS[form])
+    init_developed(s, torch, np)
+    best = s.autotune(trial_steps=trial_steps)
+    torch.cuda.synchronize()
+    s.close()
+    torch.cuda.empty_cache()
+    return best
+
+
 def run_batch(H, torch, np, args):
     """Batched workload: every form advances all channels in one launch per
-    class and stage (default launch configuration: direct launches, classes
-    in turn on one stream); compared with the FP64 form stepping each channel
-    as its own solver (timed on a sample of channels)."""
+    class and stage (or per class and step with step fusion); compared with
+    the FP64 form stepping each channel as its own solver (timed on a
+    sample of channels).  Legs: each form in the default launch
+    configuration (direct launches, classes in turn on one stream); the FP64
+    form with fused steps; and each form in the configuration hhlb_autotune
+    picks on every 8th channel, replayed as HIP graphs when it chooses them."""
     chans = batch_workload(args.batch_channels)
     nu_step = sum(c.V * c.Nx for c in chans)
     out = {"workload": f"{len(chans)} channels, Nx~U{{64..1024}}, Q~U{{4,8,12}}, log10 Kn~U[-3,1], "
                        "g~U[-1,0], T_right/T_left~U[1,2] (PCG64 seed 0), uniform grid, WENO5+RK3, "
                        "f and chi, dt=min(CFL 0.5, Kn/2), smoothly modulated start",
            "node_updates_per_step": nu_step, "steps": args.batch_steps, "forms": {}}
+    legs = [("fp64", "fp64", {}), ("fp64_fused", "fp64", {"step_fusion": 1}), ("mixed_f32", "mixed_f32", {})]
+    if not args.no_batch_tune:
+        for form in ("fp64", "mixed_f32"):
+            print(f"[bench] batch {form}: autotune on every 8th channel", file=sys.stderr, flush=True)
+            best = tune_on_sample(H, torch, np, chans, form)
+            legs.append((f"{form}_tuned", form, {k: best[k] for k in TUNING_KEYS}))
     ref = None
-    for form in ("fp64", "mixed_f32"):
+    for name, form, tuning in legs:
         s = H.Solver(chans, precision=H.PRECISIONS[form])
+        if tuning:
+            s.set_tuning(**tuning)
         mass0 = init_developed(s, torch, np)
-        print(f"[bench] batch {form}: {len(chans)} channels, {args.batch_steps} steps",
+        print(f"[bench] batch {name}: {len(chans)} channels, {args.batch_steps} steps",
               file=sys.stderr, flush=True)
-        best = s.tuning()   # the default launch configuration
+        used = s.tuning()
         s.step(args.warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -139,15 +175,16 @@ def run_batch(H, torch, np, args):
         nw, mass, bad = s.diagnostics()
         mom = s.moments()
         torch.cuda.synchronize()
-        assert int(bad.item()) == 0, f"batch {form}: non-finite populations"
+        assert int(bad.item()) == 0, f"batch {name}: non-finite populations"
+        used.pop("ms_per_step", None)
         rec = {"value": nu_step * args.batch_steps / (ms / 1e3), "unit": "node-updates/s",
-               "ms_per_step": ms / args.batch_steps, "tuning": best,
+               "ms_per_step": ms / args.batch_steps, "tuning": used,
                "mass_drift": float(((mass - mass0) / mass0).abs().max().item())}
-        if form == "fp64":
+        if name == "fp64":
             ref = mom
         else:
             rec["err_vs_fp64"] = moment_diff(np, ref, mom)
-        out["forms"][form] = rec
+        out["forms"][name] = rec
         s.close()
         del mom
         torch.cuda.empty_cache()
@@ -177,7 +214,8 @@ def run_batch(H, torch, np, args):
                                           f"{steps} steps each, launched one after another"}
     out["batched_vs_per_instance"] = {f: round(r["value"] / out["per_instance_fp64"]["value"], 1)
                                       for f, r in out["forms"].items()}
-    out["mixed_vs_fp64_batched"] = round(out["forms"]["mixed_f32"]["value"] / out["forms"]["fp64"]["value"], 3)
+    out["vs_fp64_batched"] = {f: round(r["value"] / out["forms"]["fp64"]["value"], 3)
+                              for f, r in out["forms"].items() if f != "fp64"}
     return out
 
 
@@ -374,7 +412,8 @@ def cpu_baseline(H, torch, np, forms, steps, n_parity=4, max_threads=16):
     starts = [start(c) for c in range(n_parity)]
     errs = {}
     for form in forms:
-        s = H.Solver(chans[:n_parity], precision=H.PRECISIONS[form])
+        s = H.Solver(chans[:n_parity], precision=form_precision(H, form))
+        s.set_tuning(**form_tuning(form))
         for k, (oc, _, _) in enumerate(starts):
             assert abs(s.dt[k] - oc.dt) <= 4.5e-16 * oc.dt, (form, k, s.dt[k], oc.dt)
         f = torch.from_numpy(np.concatenate([st[1].ravel() for st in starts])).cuda()
@@ -401,8 +440,8 @@ def cpu_baseline(H, torch, np, forms, steps, n_parity=4, max_threads=16):
 def run_form(H, torch, np, chans, form, args):
     """Warm up, time args.steps steps of one arithmetic form; return its
     record and the final moments (device tensors)."""
-    s = H.Solver(chans, precision=H.PRECISIONS[form])
-    s.set_tuning(waves_per_window=args.waves_per_window)
+    s = H.Solver(chans, precision=form_precision(H, form))
+    s.set_tuning(waves_per_window=args.waves_per_window, **form_tuning(form))
     mass0 = init_developed(s, torch, np)
     print(f"[bench] {form}: {len(chans)} channels x Nx={NX}, V={2 * Q}; workspace "
           f"{s.ws_bytes / 2**30:.2f} GiB; warmup {args.warmup}", file=sys.stderr, flush=True)
@@ -426,27 +465,32 @@ def run_form(H, torch, np, chans, form, args):
     mass_err = float(((mass - mass0) / mass0).abs().max().item())   # relative, from the start
     node_updates = sum(c.V * c.Nx for c in chans) * args.steps
     value = node_updates / (ms / 1e3)
-    # dominant kernel: the stage kernel (every launch of the timed region)
-    n_launch = 3 * args.steps * launches
+    # dominant kernel: the stage kernel (every launch of the timed region),
+    # or the fused-step kernel (one launch per class and step)
+    per_step = 1 if form == "fp64_fused" else 3
+    n_launch = per_step * args.steps * launches
     avg_launch_s = ms / 1e3 / n_launch
     nu_per_launch = sum(c.V * c.Nx for c in chans) / launches
-    bpl = bytes_per_node_update(form) / 3 * nu_per_launch
+    bpl = bytes_per_node_update(form) / per_step * nu_per_launch
     nc = mean_ladder_points(s, mom, np)
-    fpl = flops_per_node_update(nc=nc) / 3 * nu_per_launch
+    # the fused kernel also computes its halo lanes: 64 lanes per 46 outputs
+    redundancy = 64.0 / 46.0 if form == "fp64_fused" else 1.0
+    fpl = flops_per_node_update(nc=nc) * redundancy / per_step * nu_per_launch
     gbs = bpl / avg_launch_s / 1e9
     tfs = fpl / avg_launch_s / 1e12
     # the scope's roof for this streaming stencil is HBM (128 B per
     # node-update in FP64, 72 in the mixed forms); the vector-ALU fraction of
     # the executed flop count rides along
-    kname = ("hhlb::stage_kernel_half<16,2,0> (one RK-3 stage, FP64)" if form == "fp64" else
-             f"hhlb::stage_kernel_mixed<16,2,0,{H.PRECISIONS[form]}> (one RK-3 stage, {form})")
+    kname = {"fp64": "hhlb::stage_kernel_half<16,2,0> (one RK-3 stage, FP64)",
+             "fp64_fused": "hhlb::fused_kernel_half<16,2,0> (one whole RK-3 step, FP64)"}.get(
+        form, f"hhlb::stage_kernel_mixed<16,2,0,{form_precision(H, form)}> (one RK-3 stage, {form})")
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(form),
             "kernel": kname, "algorithmic_bytes_per_node_update": bytes_per_node_update(form),
             "algorithmic_bytes_per_launch": bpl,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
-            "alu": {"flops_per_node_update": round(flops_per_node_update(nc=nc), 1),
+            "alu": {"flops_per_node_update": round(flops_per_node_update(nc=nc) * redundancy, 1),
                     "correction_points_per_half": round(nc, 2),
                     "achieved_tflops": round(tfs, 2), "peak_tflops": FP64_VECTOR_PEAK_TFLOPS,
                     "frac": round(tfs / FP64_VECTOR_PEAK_TFLOPS, 4)},
@@ -550,13 +594,15 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp64,mixed_f32,mixed_bf16,mixed_f16",
+    ap.add_argument("--forms", default="fp64,mixed_f32,mixed_bf16,mixed_f16,fp64_fused",
                     help="arithmetic forms to time; the first is the primary line")
     ap.add_argument("--waves-per-window", type=int, default=2, choices=(2, 4),
                     help="stage-kernel shape for the large workload (4: FP64 four-wave kernel)")
     ap.add_argument("--batch-channels", type=int, default=4096,
                     help="channels of the batched uneven workload (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--no-batch-tune", action="store_true",
+                    help="skip the autotuned legs of the batched workload")
     ap.add_argument("--instance-sample", type=int, default=64)
     ap.add_argument("--instance-steps", type=int, default=20)
     ap.add_argument("--steady", action="store_true",

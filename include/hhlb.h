@@ -223,7 +223,8 @@ hhlb_status hhlb_autotune(hhlb_solver *s, int32_t trial_steps, hhlb_tuning *best
 hhlb_status hhlb_set_graph_steps(hhlb_solver *s, int32_t steps_per_graph);
 
 /* Copy the state out (device pointers, boundary layout, FP64).  chi_dev may
- * be NULL.  Asynchronous on the stream. */
+ * be NULL; the chi of a channel with Dt = 0 reads as zero.  Asynchronous on
+ * the stream. */
 hhlb_status hhlb_get_state(const hhlb_solver *s, double *f_dev, double *chi_dev);
 
 /* Moments of Eq. (fmoms) per cell, with chi's transverse energy in T:

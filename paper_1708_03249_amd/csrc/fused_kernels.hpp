@@ -9,17 +9,14 @@
 // Window geometry.  Lane l holds cell c0 + l.  Each stage's WENO-5 stencil
 // reaches 3 cells, so a lane's value stays exact for one stage less per 3
 // lanes from an edge of the window that is not a wall: a window whose edges
-// are interior keeps 9 halo lanes on each side and writes the 46 cells of
-// lanes 9..54.  At a wall the closure (Sec. IV.C.3) rebuilds the 3 ghosts
-// from the current stage every stage, exactly as the per-stage kernel does,
-// so nothing is lost there: the left-wall window (first output cell 0) starts
-// at cell -3 and writes from lane 3; the right-wall window ends with cell
-// Nx-1 at lane 60 or below, its ghosts on the lanes after it.  A window
-// starting at output cell i0 has
-//   left halo hl = 3 (i0 = 0) or 9,
-//   the right wall inside when Nx - i0 <= 61 - hl (then it writes Nx - i0
-//   cells), else an interior right edge (55 - hl cells),
-// which the host's window list follows.
+// are interior keeps 9 halo lanes on each side and writes at most the 46
+// cells of lanes 9..54.  At a wall the closure (Sec. IV.C.3) rebuilds the
+// ghosts from the current stage every stage, exactly as the per-stage kernel
+// does, so nothing is lost there.  The faces the method needs read the first
+// two ghosts only, so a wall may sit where just two ghost lanes fit (cell 0
+// at lane 2 or 3; cell Nx-1 at lane 61 or below).  The host builds each
+// channel's windows (fused_windows) so that every window edge is either such
+// a wall or lies inside the channel with its whole halo.
 //
 // Per stage the arithmetic is that of stage_kernel_half: the same closure,
 // moments, equilibrium, force block, BGK, face values and combination
@@ -49,18 +46,17 @@ constexpr int kFusedHalo = 3 * kHalo;   // halo lanes of an interior window edge
 #endif
 constexpr int kQmaxFused = HHLB_FUSED_QMAX;
 
-// Output cells of the fused window starting at output cell i0 (host and
-// device use the same rule).
-__host__ __device__ __forceinline__ int fused_window_cells(int i0, int Nx) {
-  const int hl = i0 == 0 ? kHalo : kFusedHalo;
-  return Nx - i0 <= 61 - hl ? Nx - i0 : 55 - hl;
-}
+// One window of the fused kernel: channel, first output cell, cell of lane
+// 0 and the number of output cells (lanes i0 - c0 .. i0 - c0 + nout - 1).
+struct DevFusedWindow {
+  int32_t ch, i0, c0, nout;
+};
 
 template <int Q, int NFUN, int ADV>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(
     Q <= 4 ? HHLB_FUSED_WAVES_SMALL : HHLB_FUSED_WAVES_LARGE))) void fused_kernel_half(
     StageArgs A, const DevTables *__restrict__ tb, const DevChannel *__restrict__ chans,
-    const DevWindow *__restrict__ wins, const double *__restrict__ inv_dx,
+    const DevFusedWindow *__restrict__ wins, const double *__restrict__ inv_dx,
     const double *__restrict__ gw, const double *__restrict__ in_f,
     const double *__restrict__ in_c) {
   constexpr int H = Q;
@@ -74,14 +70,13 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(
   const int hw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int w = A.xcd_map ? xcd_window(blockIdx.x, A.nwin) : (int)blockIdx.x;
-  const DevWindow win = wins[w];
+  const DevFusedWindow win = wins[w];
   const DevChannel C = chans[win.ch];
   const int Nx = C.Nx;
-  const int hl = win.i0 == 0 ? kHalo : kFusedHalo;
-  const int c0 = win.i0 - hl;                        // cell of lane 0
-  const int nout = fused_window_cells(win.i0, Nx);
-  const bool needL = win.i0 == 0;                    // the walls inside the window
-  const bool needR = win.i0 + nout == Nx;
+  const int c0 = win.c0;                             // cell of lane 0
+  const int hl = win.i0 - c0, nout = win.nout;       // output lanes hl .. hl + nout - 1
+  const bool needL = c0 < 0;                         // the walls inside the window
+  const bool needR = Nx - 1 - c0 <= 61;
   const int i = c0 + lane;
   const bool inside = i >= 0 && i < Nx;
   const int ic = inside ? i : 0;                     // clamped cell index: loads stay in bounds
@@ -126,7 +121,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(
     double nw_mine = 0.0;
     if ((hw == 1 && needL) || (hw == 0 && needR)) {
       const bool left = hw == 1;
-      const int l0 = left ? kHalo : Nx - 1 - c0;   // lane of the wall cell
+      const int l0 = left ? -c0 : Nx - 1 - c0;     // lane of the wall cell
       const int dl = left ? 1 : -1;
       const int gi = left ? -i : i - Nx + 1;       // ghost order 1..3 (else <= 0)
       const double e0 = gi == 1 ? 3.0 : (gi == 2 ? 6.0 : 10.0);

@@ -231,6 +231,18 @@ __global__ void convert_kernel(const hhlb::DevTables *tbs, const int32_t *ch_cla
 
 __global__ void zero_kernel(int32_t *p) { *p = 0; }
 
+// chi of the channels without transverse degrees of freedom (Dt = 0): the
+// kernels never advance it, so the boundary reports it as zero.
+__global__ void zero_chi_kernel(const hhlb::DevChannel *chans, const int32_t *ch_V, int n_ch, double *chi) {
+  const int ch = blockIdx.y;
+  if (ch >= n_ch) return;
+  const hhlb::DevChannel C = chans[ch];
+  if (C.half_Dt != 0.0) return;
+  const int64_t total = (int64_t)ch_V[ch] * C.Nx;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x)
+    chi[C.off + j] = 0.0;
+}
+
 }  // namespace
 
 // ---- solver ---------------------------------------------------------------
@@ -245,7 +257,7 @@ struct ModelClass {
   Launcher fused = nullptr;     // one launch per RK-3 step (FP64 half range), if built
   std::vector<hhlb::DevWindow> windows;
   size_t win_off = 0;  // byte offset in workspace
-  std::vector<hhlb::DevWindow> fwindows;   // the fused kernel's windows (9-cell halos)
+  std::vector<hhlb::DevFusedWindow> fwindows;   // the fused kernel's windows (9-cell halos)
   size_t fwin_off = 0;
   // Q > 16 (half-range Hermite, FP64): the node-parallel stage, whose tables
   // (DevLarge, then KinT and HWs) live in their own workspace block
@@ -265,6 +277,7 @@ struct hhlb_solver {
   std::vector<int32_t> Vs;
   int64_t total_state = 0, total_cells = 0;
   bool has_chi = false;
+  bool any_dt0 = false;   // some channel has Dt = 0 (no chi of its own)
   int precision = HHLB_FP64;
   size_t esize = sizeof(double);   // bytes per stored population
   hipStream_t stream = nullptr;
@@ -397,6 +410,38 @@ float round_bf16(float x) {
   return y;
 }
 float round_f16(float x) { return (float)(_Float16)x; }
+
+// Windows of the fused-step kernel for one channel of Nx cells.  A window's
+// edge is a wall whose first two ghosts fit in the 64 lanes, or lies inside
+// the channel with its whole 9-lane halo (lane 63 at a cell).
+//  - Nx <= 58: one window, both walls, three ghosts each (c0 = -3);
+//    Nx = 59, 60: one window with two ghosts per wall (c0 = -2);
+//  - else a left-wall window (c0 = -3, 52 cells on lanes 3..54), interior
+//    windows of 46 cells (c0 = first cell - 9), and a right-wall window
+//    once at most 53 cells remain (cell Nx-1 at lane <= 61).
+//  An interior edge needs at least 55 remaining cells after the window's
+//  first output; a window takes one cell less whenever the remainder would
+//  be exactly 54, which neither kind of window can start from.
+void fused_windows(int ch, int Nx, std::vector<hhlb::DevFusedWindow> &w) {
+  if (Nx <= 60) {
+    w.push_back({ch, 0, Nx <= 58 ? -3 : -2, Nx});
+    return;
+  }
+  int o = 0;
+  bool first = true;
+  for (;;) {
+    const int R = Nx - o;
+    if (!first && R <= 53) {
+      w.push_back({ch, o, o - 9, R});
+      return;
+    }
+    int m = first ? 52 : 46;
+    if (R - m == 54) --m;
+    w.push_back({ch, o, first ? -3 : o - 9, m});
+    o += m;
+    first = false;
+  }
+}
 
 // Device tables of one model class (quadrature, Q, N, p0).
 hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb::Rule &r, hhlb::DevTables &d) {
@@ -788,6 +833,7 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
       s->cell_off[c] = (int32_t)s->total_cells;
       s->total_cells += h.Nx;
       if (h.transverse_dof > 0) s->has_chi = true;
+      else s->any_dt0 = true;
     }
     s->total_state = s->off[n_ch];
     if (s->total_cells > INT32_MAX / 2) return fail(HHLB_E_UNSUPPORTED, "too many cells");
@@ -839,8 +885,7 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
       d.inv_1pDt = 1.0 / (1.0 + h.transverse_dof);
       s->dch.push_back(d);
       for (int i0 = 0; i0 < h.Nx; i0 += hhlb::kWin) mc.windows.push_back({c, i0});
-      if (mc.fused)
-        for (int i0 = 0; i0 < h.Nx; i0 += hhlb::fused_window_cells(i0, h.Nx)) mc.fwindows.push_back({c, i0});
+      if (mc.fused) fused_windows(c, h.Nx, mc.fwindows);
     }
     // workspace layout
     size_t o = 0;
@@ -851,7 +896,7 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
     s->o_V = take(sizeof(int32_t) * n_ch);
     for (auto &mc : s->classes) {
       mc.win_off = take(sizeof(hhlb::DevWindow) * mc.windows.size());
-      mc.fwin_off = take(sizeof(hhlb::DevWindow) * mc.fwindows.size());
+      mc.fwin_off = take(sizeof(hhlb::DevFusedWindow) * mc.fwindows.size());
     }
     s->o_dx = take(sizeof(double) * s->total_cells);
     s->o_invdx = take(sizeof(double) * s->total_cells);
@@ -913,8 +958,8 @@ hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr) {
     HIP_TRY(hipMemcpyAsync(ws + mc.win_off, mc.windows.data(), sizeof(hhlb::DevWindow) * mc.windows.size(),
                            hipMemcpyHostToDevice, s->stream));
     if (!mc.fwindows.empty())
-      HIP_TRY(hipMemcpyAsync(ws + mc.fwin_off, mc.fwindows.data(), sizeof(hhlb::DevWindow) * mc.fwindows.size(),
-                             hipMemcpyHostToDevice, s->stream));
+      HIP_TRY(hipMemcpyAsync(ws + mc.fwin_off, mc.fwindows.data(),
+                             sizeof(hhlb::DevFusedWindow) * mc.fwindows.size(), hipMemcpyHostToDevice, s->stream));
     if (mc.large)
       HIP_TRY(hipMemcpyAsync(ws + mc.lbl_off, mc.lblob.data(), mc.lblob.size(), hipMemcpyHostToDevice, s->stream));
   }
@@ -998,6 +1043,11 @@ hhlb_status hhlb_get_state(const hhlb_solver *s, double *f_dev, double *chi_dev)
     HIP_TRY(hipGetLastError());
   }
   if (chi_dev && !s->has_chi) HIP_TRY(hipMemsetAsync(chi_dev, 0, sizeof(double) * s->total_state, s->stream));
+  if (chi_dev && s->has_chi && s->any_dt0) {
+    const AuxArgs a = aux(s);
+    hipLaunchKernelGGL(zero_chi_kernel, state_grid(s), dim3(256), 0, s->stream, a.chans, a.ch_V, a.n_ch, chi_dev);
+    HIP_TRY(hipGetLastError());
+  }
   return HHLB_OK;
 }
 
@@ -1098,7 +1148,7 @@ void enqueue_class_fused(hhlb_solver *s, size_t ci, const void *inf, const void 
   std::memset(&a, 0, sizeof a);
   a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables) + ci;
   a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
-  a.wins = (const hhlb::DevWindow *)(s->ws + mc.fwin_off);
+  a.wins = (const hhlb::DevWindow *)(s->ws + mc.fwin_off);   // DevFusedWindow records
   a.nwin = (int32_t)mc.fwindows.size();
   a.stage = 2;
   a.xcd_map = s->tuning.xcd_map;

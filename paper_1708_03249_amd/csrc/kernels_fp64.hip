@@ -23,8 +23,9 @@ void launch_quarter(const StageArgs &a, hipStream_t s) {
 
 template <int Q, int NF, int ADV>
 void launch_fused(const StageArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((fused_kernel_half<Q, NF, ADV>), dim3(a.nwin), dim3(128), 0, s, a, a.tb, a.chans, a.wins,
-                     a.inv_dx, a.gw, (const double *)a.in_f, (const double *)a.in_c);
+  hipLaunchKernelGGL((fused_kernel_half<Q, NF, ADV>), dim3(a.nwin), dim3(128), 0, s, a, a.tb, a.chans,
+                     reinterpret_cast<const DevFusedWindow *>(a.wins), a.inv_dx, a.gw, (const double *)a.in_f,
+                     (const double *)a.in_c);
 }
 
 template <int QUAD, int Q>

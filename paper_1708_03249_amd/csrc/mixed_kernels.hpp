@@ -145,6 +145,60 @@ __device__ __forceinline__ float weno5f_lanes(float y, const FaceCoefF &c, bool 
   }
   return fmaf(wL, FL, fmaf(wC, fC, wR * FR)) * __builtin_amdgcn_rcpf(dd);
 }
+// The same face values as deviations from the upwind cell's own value:
+// returns fv - y (exact arithmetic), with dm = y_{i-1} - y_i and
+// dp = y_{i+1} - y_i.  Every candidate and smoothness indicator is formed
+// from these neighbour differences, which are exact in FP32 for neighbours
+// within a factor two of each other, instead of from the values themselves:
+// the rounding then scales with the differences rather than with y, and the
+// flux difference the stage needs, v (y_i - y_{i-+1}) + v (dev_i - dev_{i-+1}),
+// inherits that accuracy.
+__device__ __forceinline__ float weno5f_lanes_dev(float y, const FaceCoefF &c, bool used, float &dm, float &dp) {
+  const float ym = dpp_shr1f(y), yp = dpp_shl1f(y);
+  dm = ym - y;
+  dp = yp - y;
+  const float D2 = dm + dp;
+  const float E = (float)kHalfKappa * (dp - dm);
+  const float A = D2 * D2;
+  const float bC = fmaf(E, E, A);
+  const float tL = fmaf((float)kKappa, D2, E), tR = fmaf((float)kKappa, D2, -E);
+  const float bL = fmaf(tL, tL, A), bR = fmaf(tR, tR, A);
+  // candidates of this lane's triple as deviations from the value of the
+  // lane they are shifted to: y_m - y_{m+1} = -dp (to the right neighbour),
+  // y_m - y_{m-1} = -dm (to the left one)
+  const float fL = fmaf(c.gl, D2, fmaf(c.el, E, -dp));
+  const float fC = fmaf(1.0f / 12.0f, D2, c.ec * E);
+  const float fR = fmaf(c.gr, D2, fmaf(c.er, E, -dm));
+  const float sL = dpp_shr1f(bL), FL = dpp_shr1f(fL);
+  const float sR = dpp_shl1f(bR), FR = dpp_shl1f(fR);
+  const int ex = __builtin_amdgcn_frexp_expf(fmaxf(sL, fmaxf(bC, sR)));
+  const float rL = ldexpf(sL, -ex), rC = ldexpf(bC, -ex), rR = ldexpf(sR, -ex);
+  const float qL = rL * rL, qC = rC * rC, qR = rR * rR;
+  float wL = c.dl * (qC * qR), wC = c.dc * (qL * qR), wR = c.dr * (qL * qC);
+  float dd = wL + wC + wR;
+  if (!(dd > 1e-37f) && used) {   // limit rule, as in weno5f
+    const float tiny = 1e-17f;
+    wL = qL < tiny ? c.dl : 0.0f;
+    wC = qC < tiny ? c.dc : 0.0f;
+    wR = qR < tiny ? c.dr : 0.0f;
+    dd = wL + wC + wR;
+  }
+  return fmaf(wL, FL, fmaf(wC, fC, wR * FR)) * __builtin_amdgcn_rcpf(dd);
+}
+__device__ __forceinline__ float upwind3f_lanes_dev(float y, const FaceCoefF &c, float &dm, float &dp) {
+  const float ym = dpp_shr1f(y), yp = dpp_shl1f(y);
+  dm = ym - y;
+  dp = yp - y;
+  const float D2 = dm + dp;
+  const float E = (float)kHalfKappa * (dp - dm);
+  return fmaf(1.0f / 12.0f, D2, c.ec * E);
+}
+template <int ADV>
+__device__ __forceinline__ float face_dev_f_lanes(float y, const FaceCoefF &c, bool used, float &dm, float &dp) {
+  if constexpr (ADV == 0) return weno5f_lanes_dev(y, c, used, dm, dp);
+  else return upwind3f_lanes_dev(y, c, dm, dp);
+}
+
 __device__ __forceinline__ float upwind3f_lanes(float y, const FaceCoefF &c) {
   const float ym = dpp_shr1f(y), yp = dpp_shl1f(y);
   const float D2 = fmaf(-2.0f, y, ym) + yp;
@@ -646,11 +700,16 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
       if (sec + PD < NSEC) fetch(sec + PD, sec % PD);
       const float y0v = fn == 0 ? yf[j] : yc[j];
       const float src = fn == 0 ? srcf[j] : srcc[j];
-      float fv = face_value_f_lanes<ADV>(y0v, fcoef, face_used);
-      if (wall_face) fv = y0v;
-      const float F = v * fv;
-      const float Fo = hw == 0 ? dpp_shr1f(F) : dpp_shl1f(F);
-      const float L = fmaf(sdx, F - Fo, src);
+      // flux difference from the face values' deviations: F_i - F_other =
+      // v (y_i - y_other) + v (dev_i - dev_other), the other face's lane being
+      // i-1 (hw = 0) or i+1 (hw = 1); the wall face's value is imposed as the
+      // ghost itself (deviation 0)
+      float dm, dp;
+      float dev = face_dev_f_lanes<ADV>(y0v, fcoef, face_used, dm, dp);
+      if (wall_face) dev = 0.0f;
+      const float Fd = v * dev;
+      const float Fdo = hw == 0 ? dpp_shr1f(Fd) : dpp_shl1f(Fd);
+      const float L = fmaf(sdx, fmaf(v, hw == 0 ? -dm : -dp, Fd - Fdo), src);
       const float inc = b_inc * (din + dt * L);
       if (!last) {
         if (out_lane) row((float *)(fn == 0 ? A.out_f : A.out_c), j)[ic] = inc;

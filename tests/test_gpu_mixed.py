@@ -77,7 +77,8 @@ def test_mixed_forms_against_oracle(case):
 def test_mixed_forms_batched_sample_smallest_kn():
     """Channels of the batched workload (PCG64 seed 0) with the smallest Kn
     (down to about 1e-3, dt = Kn/2, so dt/tau = n/2: the stiffest collision
-    of the set), one of the largest Kn and the first channel, from the
+    of the set), one of the largest Kn, the first channel and the channel
+    where the mixed and FP64 forms differ most, from the
     benchmark's developed start (equilibrium times the seeded smooth
     modulation) for 1000 steps: every mixed form against the oracle within
     1e-5 in n, u and T."""
@@ -87,8 +88,11 @@ def test_mixed_forms_batched_sample_smallest_kn():
     h = H()
     draws = batch_draws(4096, 0)
     short = [k for k, d in enumerate(draws) if d["Nx"] <= 256]
+    # the three smallest Kn, the largest, the first channel, and channel 3526
+    # (Q = 4, Kn = 4.6: the largest mixed-against-FP64 moment difference of
+    # the whole batch after 1000 steps)
     pick = sorted(short, key=lambda k: draws[k]["Kn"])[:3] + \
-        [max(short, key=lambda k: draws[k]["Kn"]), 0]
+        [max(short, key=lambda k: draws[k]["Kn"]), 0, 3526]
     chans = [h.Channel(quad=h.HALF_HERMITE, Q=draws[k]["Q"], N=draws[k]["Q"] - 1, Nx=draws[k]["Nx"],
                        adv=h.WENO5, transverse_dof=2, Kn=draws[k]["Kn"], g=draws[k]["g"],
                        T_right=draws[k]["T_right"], dt=-0.5) for k in pick]

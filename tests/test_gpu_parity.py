@@ -506,6 +506,19 @@ def test_step_fusion_small_channel_and_edges():
     _check(chans, 60, perturb=0.03, seed=17, what="fused: small and edge", tuning=FUSED)
 
 
+def test_step_fusion_window_edges():
+    """Channel lengths at the edges of the fused kernel's window rules: one
+    window with three (Nx = 8, 58) or two (59, 60) ghosts per wall; 61 (a
+    left-wall and a right-wall window); 106 (a remainder of 54 cells after
+    the first window, which it avoids); 152 and 428 (interior windows whose
+    halo ends next to the right wall's ghosts)."""
+    h = H()
+    chans = [h.Channel(quad=h.HALF_HERMITE, Q=4, Nx=nx, adv=h.WENO5, transverse_dof=2, Kn=0.08,
+                       g=-0.4, T_left=1.0, T_right=1.3, dt=-0.5)
+             for nx in (8, 58, 59, 60, 61, 106, 107, 152, 428)]
+    _check(chans, 30, perturb=0.03, seed=29, what="fused: window edges", tuning=FUSED)
+
+
 @pytest.mark.parametrize("Q", [4, 8, 12, 16])
 def test_step_fusion_stretched_weno5(Q):
     """Fused steps on stretched WENO-5 channels with unequal walls at three
