@@ -41,6 +41,11 @@
 #ifndef HHLB_MIXED_WAVES
 #define HHLB_MIXED_WAVES 4
 #endif
+// 1: keep the prologue's stage increments in registers for the combination
+// instead of loading them again in pass 2
+#ifndef HHLB_MIXED_KEEP_D
+#define HHLB_MIXED_KEEP_D 0
+#endif
 
 namespace hhlb {
 
@@ -392,16 +397,28 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
   const bool has_d = A.stage != 0;
   const int64_t rbase = C.off + (int64_t)kb0 * Nx;
   float yf[H], yc[NC > 1 ? H : 1];
+#if HHLB_MIXED_KEEP_D
+  // the stage increments stay in registers for the combination of pass 2
+  float kdf[H], kdc[NC > 1 ? H : 1];
+#endif
 #pragma unroll
   for (int j = 0; j < H; ++j) {
     const int64_t o = rbase + (int64_t)j * Nx + i;
-    yf[j] = inside ? hi_f[o] + (has_d ? d_f[o] : 0.0f) : 0.0f;
+    const float dv = inside && has_d ? d_f[o] : 0.0f;
+    yf[j] = inside ? hi_f[o] + dv : 0.0f;
+#if HHLB_MIXED_KEEP_D
+    kdf[j] = dv;
+#endif
   }
   if constexpr (NC > 1) {
 #pragma unroll
     for (int j = 0; j < H; ++j) {
       const int64_t o = rbase + (int64_t)j * Nx + i;
-      yc[j] = inside ? hi_c[o] + (has_d ? d_c[o] : 0.0f) : 0.0f;
+      const float dv = inside && has_d ? d_c[o] : 0.0f;
+      yc[j] = inside ? hi_c[o] + dv : 0.0f;
+#if HHLB_MIXED_KEEP_D
+      kdc[j] = dv;
+#endif
     }
   }
 
@@ -677,7 +694,11 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
   auto fetch = [&](int sec, int slot) {
     const int r = sec / NC;
     const bool f0 = (sec % NC) == 0;
+#if HHLB_MIXED_KEEP_D
+    dq[slot] = 0.0f;
+#else
     dq[slot] = has_d ? row(f0 ? d_f : d_c, r)[ic] : 0.0f;
+#endif
     if (last) {
       hq[slot] = row(f0 ? hi_f : hi_c, r)[ic];
       lq[slot] = row(f0 ? A.lo_in_f : A.lo_in_c, r)[ic];
@@ -695,7 +716,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
 #pragma unroll
     for (int fn = 0; fn < NC; ++fn) {
       const int sec = j * NC + fn;
-      const float din = dq[sec % PD], hi = hq[sec % PD];
+#if HHLB_MIXED_KEEP_D
+      const float din = fn == 0 ? kdf[j] : kdc[NC > 1 ? j : 0];
+#else
+      const float din = dq[sec % PD];
+#endif
+      const float hi = hq[sec % PD];
       const int16_t lo = lq[sec % PD];
       if (sec + PD < NSEC) fetch(sec + PD, sec % PD);
       const float y0v = fn == 0 ? yf[j] : yc[j];
