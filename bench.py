@@ -120,7 +120,7 @@ def init_developed(s, torch, np, seed=0, amplitude=0.05):
     return mass0.clone()
 
 
-TUNING_KEYS = ("graph_steps", "class_streams", "xcd_map", "waves_per_window", "step_fusion")
+TUNING_KEYS = ("graph_steps", "class_streams", "xcd_map", "waves_per_window", "step_fusion", "merge_classes")
 
 
 def tune_on_sample(H, torch, np, chans, form, trial_steps=10, stride=8):
@@ -141,7 +141,9 @@ def run_batch(H, torch, np, args):
     the FP64 form stepping each channel as its own solver (timed on a
     sample of channels).  Legs: each form in the default launch
     configuration (direct launches, classes in turn on one stream); the FP64
-    form with fused steps; and each form in the configuration hhlb_autotune
+    form with fused steps; the FP64 form with one launch per stage across
+    its classes (a block per window, and persistent blocks), replayed as
+    16-step HIP graphs; and each form in the configuration hhlb_autotune
     picks on every 8th channel, replayed as HIP graphs when it chooses them."""
     chans = batch_workload(args.batch_channels)
     nu_step = sum(c.V * c.Nx for c in chans)
@@ -149,7 +151,10 @@ def run_batch(H, torch, np, args):
                        "g~U[-1,0], T_right/T_left~U[1,2] (PCG64 seed 0), uniform grid, WENO5+RK3, "
                        "f and chi, dt=min(CFL 0.5, Kn/2), smoothly modulated start",
            "node_updates_per_step": nu_step, "steps": args.batch_steps, "forms": {}}
-    legs = [("fp64", "fp64", {}), ("fp64_fused", "fp64", {"step_fusion": 1}), ("mixed_f32", "mixed_f32", {})]
+    legs = [("fp64", "fp64", {}), ("fp64_fused", "fp64", {"step_fusion": 1}),
+            ("fp64_one_launch", "fp64", {"merge_classes": 1, "graph_steps": 16}),
+            ("fp64_persistent", "fp64", {"merge_classes": 2, "graph_steps": 16}),
+            ("mixed_f32", "mixed_f32", {})]
     if not args.no_batch_tune:
         for form in ("fp64", "mixed_f32"):
             print(f"[bench] batch {form}: autotune on every 8th channel", file=sys.stderr, flush=True)
@@ -179,6 +184,7 @@ def run_batch(H, torch, np, args):
         used.pop("ms_per_step", None)
         rec = {"value": nu_step * args.batch_steps / (ms / 1e3), "unit": "node-updates/s",
                "ms_per_step": ms / args.batch_steps, "tuning": used,
+               "launches_per_stage": s.launch_info()[0],
                "mass_drift": float(((mass - mass0) / mass0).abs().max().item())}
         if name == "fp64":
             ref = mom
@@ -294,13 +300,19 @@ def ladder_points(counts, reach, y):
     """Correction points per half that the equilibrium's ladder (counts,
     reach from hhlb_equilibrium_ladder) selects for a wave whose largest
     |y0| = |u| sqrt(m/T) is y: the smallest count whose calibrated reach
-    covers y (the top count beyond it, per panel)."""
+    covers y; beyond the top count's reach, the top count on the smallest
+    power-of-two number of panels (at most 64) that covers it."""
     if y <= 0:
         return 0
     for n, r in zip(counts[1:], reach[1:]):
         if r >= y:
             return n
-    return counts[-1] * max(1, math.ceil(y / reach[-1])) if reach[-1] > 0 else counts[-1]
+    if not reach[-1] > 0:
+        return counts[-1]
+    P = 2
+    while P < 64 and reach[-1] * P < y:
+        P *= 2
+    return counts[-1] * P
 
 
 def mean_ladder_points(s, mom, np):

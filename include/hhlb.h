@@ -189,6 +189,14 @@ hhlb_status hhlb_step(hhlb_solver *s, int64_t n_steps);
  *                 per stage.  The stages' arithmetic is the same; results
  *                 agree to rounding (the equilibrium's correction count is
  *                 chosen per window of cells).
+ *  merge_classes: 0 = one launch per stage for each model class; 1 = one
+ *                 launch per stage for all FP64 half-range classes that share
+ *                 the functions (f, or f and chi) and the scheme, each block
+ *                 taking one window of any of them; 2 = the same launch with
+ *                 as many blocks as the GPU holds at once, each taking
+ *                 windows in turn (persistent).  Other classes keep their own
+ *                 launches.  Needs class_streams 0, step_fusion 0 and
+ *                 waves_per_window 2 (HHLB_E_ARG otherwise).
  *  ms_per_step:   filled in by hhlb_autotune (the measured time). */
 typedef struct {
   int32_t graph_steps;
@@ -196,6 +204,7 @@ typedef struct {
   int32_t xcd_map;
   int32_t waves_per_window;
   int32_t step_fusion;
+  int32_t merge_classes;
   float ms_per_step;
 } hhlb_tuning;
 
@@ -207,7 +216,8 @@ hhlb_status hhlb_get_tuning(const hhlb_solver *s, hhlb_tuning *t);
  * (step_fusion in {0, 1} when a class has the fused-step kernel;
  * waves_per_window in {2, 4} when a class has the four-wave kernel; direct
  * launches with class_streams in {0, 1} -- 1 only when there are several
- * classes -- and graphs of 16 steps; each with xcd_map in {1, 0}) on the
+ * classes -- and graphs of 16 steps; each with xcd_map in {1, 0}; and
+ * merge_classes in {1, 2} when some classes can share a launch) on the
  * solver's own channels and keeps the fastest; *best_out (may be NULL)
  * receives it.  The trials advance the state like hhlb_step (candidates x
  * (trial_steps + 1) steps) and synchronise the stream; call it in place of
@@ -261,9 +271,10 @@ hhlb_status hhlb_equilibrium_ladder(const hhlb_solver *s, int32_t channel, int32
  * largest |y0| = |u| sqrt(m/T) lay beyond the range the correction ladder
  * of the half-range equilibrium (Sec. IV.B.3, evaluated by a change of
  * variables) was calibrated for on the host (|y0| <= 1 for the Hermite
- * sets).  Such evaluations split the correction integral into equal panels
- * of the calibrated width, up to 64 panels (|y0| up to 64 times that
- * range).  Synchronises the solver's stream; *count is a host int64. */
+ * sets).  Such evaluations split the correction integral into 2, 4, .., 64
+ * equal panels of the calibrated width (|y0| up to 64 times that range; the
+ * large-Q path uses the smallest panel count that covers it).  Synchronises
+ * the solver's stream; *count is a host int64. */
 hhlb_status hhlb_wide_equilibrium_count(const hhlb_solver *s, int64_t *count);
 
 /* Wait for the solver's streams, then release its host tables, graphs,

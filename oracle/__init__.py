@@ -28,9 +28,13 @@ WENO5, UPWIND3 = 0, 1
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fast-math).  Returns the library path."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", _SRC, "-o", _LIB,
+        # a new file replaces the old one, so processes that have the library
+        # loaded keep their copy
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", _SRC, "-o", tmp,
                "-lquadmath", "-lm"]
         subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
     return _LIB
 
 

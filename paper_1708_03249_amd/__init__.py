@@ -38,12 +38,14 @@ class HHLBError(RuntimeError):
 class _CTuning(ctypes.Structure):
     _fields_ = [("graph_steps", ctypes.c_int32), ("class_streams", ctypes.c_int32),
                 ("xcd_map", ctypes.c_int32), ("waves_per_window", ctypes.c_int32),
-                ("step_fusion", ctypes.c_int32), ("ms_per_step", ctypes.c_float)]
+                ("step_fusion", ctypes.c_int32), ("merge_classes", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_float)]
 
     def as_dict(self):
         return {"graph_steps": self.graph_steps, "class_streams": self.class_streams,
                 "xcd_map": self.xcd_map, "waves_per_window": self.waves_per_window,
-                "step_fusion": self.step_fusion, "ms_per_step": self.ms_per_step}
+                "step_fusion": self.step_fusion, "merge_classes": self.merge_classes,
+                "ms_per_step": self.ms_per_step}
 
 
 class _CChannel(ctypes.Structure):
@@ -310,9 +312,10 @@ class Solver:
     def step(self, n_steps: int):
         _check(lib().hhlb_step(self.h, int(n_steps)))
 
-    def set_tuning(self, graph_steps=0, class_streams=0, xcd_map=1, waves_per_window=2, step_fusion=0):
+    def set_tuning(self, graph_steps=0, class_streams=0, xcd_map=1, waves_per_window=2, step_fusion=0,
+                   merge_classes=0):
         t = _CTuning(int(graph_steps), int(class_streams), int(xcd_map), int(waves_per_window),
-                     int(step_fusion), 0.0)
+                     int(step_fusion), int(merge_classes), 0.0)
         _check(lib().hhlb_set_tuning(self.h, ctypes.byref(t)))
 
     def tuning(self):

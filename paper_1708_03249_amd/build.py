@@ -28,7 +28,8 @@ def _run(cmd):
 
 
 SOURCES = ("tables.cpp", "hhlb_api.hip", "kernels_fp64.hip", "kernels_mixed_f32.hip",
-           "kernels_mixed_bf16.hip", "kernels_mixed_f16.hip", "kernels_large.hip", "kernels_multi.hip")
+           "kernels_mixed_bf16.hip", "kernels_mixed_f16.hip", "kernels_large.hip", "kernels_multi.hip",
+           "kernels_classes.hip")
 
 
 def build(verbose: bool = True, out: str | None = None, defines=()) -> str:

@@ -224,20 +224,15 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(
       for (int j = 0; j < tb->nm; ++j) accum(ub + s * tb->zm[j], tb->wm[j]);
       const double ymax = wave_max(inside && live ? fabs(y0) : 0.0);
       if (ymax > 0.0) {
-        int li = kLadder - 1;
-        for (int j = 1; j < kLadder; ++j)
-          if (tb->lad_y[j] >= ymax) { li = j; break; }
+        const int li = ladder_entry(tb, ymax);
         const int ncor = tb->lad_n[li], o = tb->lad_off[li];
-        const int P = li == kLadder - 1 ? correction_panels(ymax, tb->lad_y[kLadder - 1]) : 1;
-        if (P > 1 && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
-        const double iP = 1.0 / P;
-        for (int p = 0; p < P; ++p)
-          for (int j = 0; j < ncor; ++j) {
-            const double t = (p + tb->ltau[o + j]) * iP;
-            const double yt = y0 * t;
-            const double e = y0 * (tb->llamw[o + j] * iP) * exp(-0.5 * yt * yt);
-            accum(ub * (1.0 - t), -sg * e);
-          }
+        if (ncor > tb->lad_n[kLadder - 1] && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
+        for (int j = 0; j < ncor; ++j) {
+          const double t = tb->ltau[o + j];
+          const double yt = y0 * t;
+          const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
+          accum(ub * (1.0 - t), -sg * e);
+        }
       }
     }
 

@@ -3,6 +3,7 @@
 // launch sequence of the three RK-3 stages.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -47,6 +48,7 @@ const hhlb::LaunchMap &launchers() {
     hhlb::register_mixed_f32(t);
     hhlb::register_mixed_bf16(t);
     hhlb::register_mixed_f16(t);
+    hhlb::register_classes(t);
     return t;
   }();
   return m;
@@ -306,7 +308,18 @@ struct hhlb_solver {
   bool flag_pending = false;
   // launch configuration (hhlb_set_tuning / hhlb_autotune): direct launches,
   // classes one after the other, XCD-aware window mapping by default
-  hhlb_tuning tuning = {0, 0, 1, 2, 0, 0.0f};
+  hhlb_tuning tuning = {0, 0, 1, 2, 0, 0, 0.0f};
+  // launches across classes (hhlb_tuning.merge_classes): FP64 half-range
+  // classes with the same functions and scheme take one launch per stage
+  struct MergeGroup {
+    Launcher launch = nullptr;
+    int qtop = 0;
+    std::vector<size_t> members;
+    std::vector<hhlb::DevClassWindow> wins;
+    size_t win_off = 0;
+  };
+  std::vector<MergeGroup> groups;
+  std::vector<int> class_group;        // group of each class, -1: launched alone
   std::vector<hipStream_t> cstreams;   // one per model class (class_streams)
   std::vector<hipEvent_t> cjoin;
   hipEvent_t cfork = nullptr;
@@ -545,7 +558,7 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
     }
   }
   // correction ladder (half range): point counts and the |y0| each covers
-  const int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
+  static constexpr int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
   double limits[hhlb::kLadder] = {0};
   if (hhlb::half_range(h.quad)) hhlb::correction_limits(r, N, counts, hhlb::kLadder, 3e-16, limits);
   int o = 0;
@@ -562,6 +575,32 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
       }
     }
     o += counts[j];
+  }
+  // beyond the calibrated reach: the top count on 2, 4, .., 64 equal panels of
+  // [y0, 0], each panel within the top count's reach, so the composite rule
+  // reaches that many times as far (the nodes (p + tau_q)/P, the weights
+  // lambda_q/P).  Without a calibrated top reach the entries repeat the top.
+  static_assert(hhlb::kLadderTop == counts[hhlb::kLadder - 1], "top ladder count");
+  const double ytop = limits[hhlb::kLadder - 1];
+  std::vector<long double> tt, lt;
+  hhlb::gauss_legendre01(hhlb::kLadderTop, tt, lt);
+  for (int c = 0; c < hhlb::kComposite; ++c) {
+    const int j = hhlb::kLadder + c, P = 2 << c;
+    if (!(ytop > 0.0)) {
+      d.lad_n[j] = d.lad_n[hhlb::kLadder - 1];
+      d.lad_off[j] = d.lad_off[hhlb::kLadder - 1];
+      d.lad_y[j] = ytop;
+      continue;
+    }
+    d.lad_n[j] = hhlb::kLadderTop * P;
+    d.lad_off[j] = o;
+    d.lad_y[j] = ytop * P;
+    for (int pnl = 0; pnl < P; ++pnl)
+      for (int q = 0; q < hhlb::kLadderTop; ++q) {
+        d.ltau[o + pnl * hhlb::kLadderTop + q] = (double)((pnl + tt[q]) / P);
+        d.llamw[o + pnl * hhlb::kLadderTop + q] = (double)(lt[q] / P * inv_s2pi);
+      }
+    o += hhlb::kLadderTop * P;
   }
   return HHLB_OK;
 }
@@ -887,6 +926,34 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
       for (int i0 = 0; i0 < h.Nx; i0 += hhlb::kWin) mc.windows.push_back({c, i0});
       if (mc.fused) fused_windows(c, h.Nx, mc.fwindows);
     }
+    // classes that can share a launch per stage: FP64 half-range classes of
+    // the per-stage window kernels, grouped by functions and scheme
+    s->class_group.assign(s->classes.size(), -1);
+    if (precision == HHLB_FP64) {
+      std::map<std::pair<int, int>, std::vector<size_t>> by;
+      for (size_t ci = 0; ci < s->classes.size(); ++ci) {
+        const ModelClass &mc = s->classes[ci];
+        if (!mc.large && hhlb::half_range(mc.quad) && mc.launch) by[{mc.Dt > 0 ? 2 : 1, mc.adv}].push_back(ci);
+      }
+      for (auto &kv : by) {
+        if (kv.second.size() < 2) continue;
+        int qmax = 0;
+        for (size_t ci : kv.second) qmax = std::max(qmax, s->classes[ci].Q);
+        const int qtop = qmax <= 8 ? 8 : (qmax <= 12 ? 12 : 16);
+        auto lk = launchers().find({HHLB_HALF_HERMITE, qtop, kv.first.first, kv.first.second, HHLB_FP64, 3});
+        if (lk == launchers().end()) continue;
+        hhlb_solver::MergeGroup g;
+        g.launch = lk->second;
+        g.qtop = qtop;
+        g.members = kv.second;
+        for (size_t ci : kv.second) {
+          const ModelClass &mc = s->classes[ci];
+          for (const auto &w : mc.windows) g.wins.push_back({w.ch, w.i0, (int32_t)ci, (int32_t)mc.Q});
+          s->class_group[ci] = (int)s->groups.size();
+        }
+        s->groups.push_back(std::move(g));
+      }
+    }
     // workspace layout
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r0 = o; o = align256(o + bytes); return r0; };
@@ -898,6 +965,7 @@ hhlb_status hhlb_create(const hhlb_channel *channels, int32_t n_ch, int32_t prec
       mc.win_off = take(sizeof(hhlb::DevWindow) * mc.windows.size());
       mc.fwin_off = take(sizeof(hhlb::DevFusedWindow) * mc.fwindows.size());
     }
+    for (auto &g : s->groups) g.win_off = take(sizeof(hhlb::DevClassWindow) * g.wins.size());
     s->o_dx = take(sizeof(double) * s->total_cells);
     s->o_invdx = take(sizeof(double) * s->total_cells);
     s->o_gw = take(sizeof(double) * s->gw.size());
@@ -963,6 +1031,9 @@ hhlb_status hhlb_bind_workspace(hhlb_solver *s, void *dev_ptr) {
     if (mc.large)
       HIP_TRY(hipMemcpyAsync(ws + mc.lbl_off, mc.lblob.data(), mc.lblob.size(), hipMemcpyHostToDevice, s->stream));
   }
+  for (auto &g : s->groups)
+    HIP_TRY(hipMemcpyAsync(ws + g.win_off, g.wins.data(), sizeof(hhlb::DevClassWindow) * g.wins.size(),
+                           hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(ws + s->o_dx, s->dx.data(), sizeof(double) * s->total_cells,
                          hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(ws + s->o_invdx, s->inv_dx.data(), sizeof(double) * s->total_cells,
@@ -1119,6 +1190,7 @@ void enqueue_class_stage(hhlb_solver *s, size_t ci, int stage, const void *inf, 
     return;
   }
   hhlb::StageArgs a;
+  std::memset(&a, 0, sizeof a);
   a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables) + ci;
   a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
   a.wins = (const hhlb::DevWindow *)(s->ws + mc.win_off);
@@ -1159,6 +1231,40 @@ void enqueue_class_fused(hhlb_solver *s, size_t ci, const void *inf, const void 
   a.nwall = (double *)(s->ws + s->o_nwall);
   a.wide = (unsigned long long *)(s->ws + s->o_wide);
   mc.fused(a, stream);
+}
+
+// One RK stage of the classes of merge group gi in one launch (FP64).
+void enqueue_group_stage(hhlb_solver *s, size_t gi, int stage, const void *inf, const void *inc, void *outf,
+                         void *outc, double a_base, double b_stage, hipStream_t stream) {
+  const auto &g = s->groups[gi];
+  hhlb::StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.tb = (const hhlb::DevTables *)(s->ws + s->o_tables);   // the classes' tables, indexed by class
+  a.chans = (const hhlb::DevChannel *)(s->ws + s->o_chans);
+  a.wins = (const hhlb::DevWindow *)(s->ws + g.win_off);    // DevClassWindow records
+  a.nwin = (int32_t)g.wins.size();
+  a.nblocks = s->tuning.merge_classes == 2 ? -1 : 0;
+  a.stage = stage;
+  a.xcd_map = s->tuning.xcd_map;
+  a.inv_dx = (const double *)(s->ws + s->o_invdx);
+  a.gw = (const double *)(s->ws + s->o_gw);
+  a.in_f = inf; a.in_c = inc;
+  a.base_f = s->fA(); a.base_c = s->cA();
+  a.out_f = outf; a.out_c = outc;
+  a.a_base = a_base;
+  a.b_stage = b_stage;
+  a.nwall = (double *)(s->ws + s->o_nwall);
+  a.wide = (unsigned long long *)(s->ws + s->o_wide);
+  g.launch(a, stream);
+}
+
+// One RK-3 step of merge group gi (FP64, the per-stage buffers of
+// enqueue_class_steps) from the solver's current parity (left unchanged).
+void enqueue_group_step(hhlb_solver *s, size_t gi, hipStream_t stream) {
+  const int p = s->par, q = p ^ 1;
+  enqueue_group_stage(s, gi, 0, s->hiF[p], s->hiC[p], s->hiF[q], s->hiC[q], 0.0, 1.0, stream);
+  enqueue_group_stage(s, gi, 1, s->hiF[q], s->hiC[q], s->fC, s->cC, 0.75, 0.25, stream);
+  enqueue_group_stage(s, gi, 2, s->fC, s->cC, s->hiF[q], s->hiC[q], 1.0 / 3.0, 2.0 / 3.0, stream);
 }
 
 // One RK stage of every class on one stream.
@@ -1211,8 +1317,12 @@ hhlb_status enqueue_steps(hhlb_solver *s, int64_t n_steps, hipStream_t stream, b
   const size_t nc = s->classes.size();
   if (capturing || !s->tuning.class_streams || nc < 2) {
     const int par0 = s->par;
+    const bool merge = s->tuning.merge_classes != 0;
     for (int64_t step = 0; step < n_steps; ++step) {
-      for (size_t ci = 0; ci < nc; ++ci) enqueue_class_steps(s, ci, 1, stream);
+      if (merge)
+        for (size_t gi = 0; gi < s->groups.size(); ++gi) enqueue_group_step(s, gi, stream);
+      for (size_t ci = 0; ci < nc; ++ci)
+        if (!merge || s->class_group[ci] < 0) enqueue_class_steps(s, ci, 1, stream);
       s->par ^= 1;
     }
     (void)par0;
@@ -1336,15 +1446,19 @@ extern "C" hhlb_status hhlb_set_graph_steps(hhlb_solver *s, int32_t steps_per_gr
 extern "C" hhlb_status hhlb_set_tuning(hhlb_solver *s, const hhlb_tuning *t) {
   if (!s || !t) return fail(HHLB_E_ARG, "null argument");
   if (t->graph_steps < 0 || (t->class_streams != 0 && t->class_streams != 1) || (t->xcd_map != 0 && t->xcd_map != 1) ||
-      (t->waves_per_window != 2 && t->waves_per_window != 4) || (t->step_fusion != 0 && t->step_fusion != 1))
-    return fail(HHLB_E_ARG,
-                "graph_steps >= 0, class_streams, xcd_map and step_fusion 0 or 1, waves_per_window 2 or 4");
+      (t->waves_per_window != 2 && t->waves_per_window != 4) || (t->step_fusion != 0 && t->step_fusion != 1) ||
+      t->merge_classes < 0 || t->merge_classes > 2)
+    return fail(HHLB_E_ARG, "graph_steps >= 0, class_streams, xcd_map and step_fusion 0 or 1, "
+                            "waves_per_window 2 or 4, merge_classes 0, 1 or 2");
+  if (t->merge_classes && (t->class_streams || t->step_fusion || t->waves_per_window != 2))
+    return fail(HHLB_E_ARG, "merge_classes needs class_streams 0, step_fusion 0 and waves_per_window 2");
   s->drop_graphs();
   s->tuning.graph_steps = t->graph_steps;
   s->tuning.class_streams = t->class_streams;
   s->tuning.xcd_map = t->xcd_map;
   s->tuning.waves_per_window = t->waves_per_window;
   s->tuning.step_fusion = t->step_fusion;
+  s->tuning.merge_classes = t->merge_classes;
   return HHLB_OK;
 }
 
@@ -1370,18 +1484,21 @@ extern "C" hhlb_status hhlb_autotune(hhlb_solver *s, int32_t trial_steps, hhlb_t
     for (int wpw : {2, 4})
       for (int gs : {0, 16})
         for (int cs : {0, 1})
-          for (int xm : {1, 0}) {
-            if (cs && (!multi || gs > 0)) continue;   // class streams apply to direct launches
-            if (wpw == 4 && !has4) continue;
-            if (sf && !hasf) continue;
-            hhlb_tuning t{};
-            t.graph_steps = gs;
-            t.class_streams = cs;
-            t.xcd_map = xm;
-            t.waves_per_window = wpw;
-            t.step_fusion = sf;
-            cands.push_back(t);
-          }
+          for (int xm : {1, 0})
+            for (int mg : {0, 1, 2}) {
+              if (cs && (!multi || gs > 0)) continue;   // class streams apply to direct launches
+              if (wpw == 4 && !has4) continue;
+              if (sf && !hasf) continue;
+              if (mg && (s->groups.empty() || cs || sf || wpw != 2)) continue;
+              hhlb_tuning t{};
+              t.graph_steps = gs;
+              t.class_streams = cs;
+              t.xcd_map = xm;
+              t.waves_per_window = wpw;
+              t.step_fusion = sf;
+              t.merge_classes = mg;
+              cands.push_back(t);
+            }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -1495,7 +1612,10 @@ hhlb_status hhlb_launch_info(const hhlb_solver *s, int32_t *launches_per_stage, 
   if (!s) return fail(HHLB_E_ARG, "null solver");
   if (launches_per_stage) {
     int32_t n = 0;
-    for (auto &mc : s->classes) n += mc.large ? 2 : 1;   // large classes: cell and node phase
+    const bool merge = s->tuning.merge_classes != 0;
+    for (size_t ci = 0; ci < s->classes.size(); ++ci)
+      if (!merge || s->class_group[ci] < 0) n += s->classes[ci].large ? 2 : 1;   // large: cell and node phase
+    if (merge) n += (int32_t)s->groups.size();
     *launches_per_stage = n;
   }
   if (windows_total) {

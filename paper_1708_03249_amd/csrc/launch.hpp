@@ -13,7 +13,8 @@ namespace hhlb {
 using Launcher = void (*)(const StageArgs &, hipStream_t);
 // (quadrature kind, Q, functions (1 = f, 2 = f and chi), advection, precision,
 //  shape: 2 = the two-wave stage kernels, 4 = the four-wave FP64 stage kernel,
-//  1 = the fused kernel of a whole RK-3 step)
+//  1 = the fused kernel of a whole RK-3 step, 3 = the FP64 stage kernel across
+//  classes, keyed by the largest order it holds)
 using LaunchKey = std::tuple<int, int, int, int, int, int>;
 using LaunchMap = std::map<LaunchKey, Launcher>;
 
@@ -21,6 +22,7 @@ void register_fp64(LaunchMap &m);
 void register_mixed_f32(LaunchMap &m);
 void register_mixed_bf16(LaunchMap &m);
 void register_mixed_f16(LaunchMap &m);
+void register_classes(LaunchMap &m);
 
 // The node-parallel FP64 stage of large half-range classes (Q > 16):
 // kernels_large.hip.

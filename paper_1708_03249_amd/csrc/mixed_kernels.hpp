@@ -527,6 +527,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
 #pragma unroll
   for (int l = 0; l < Q; ++l) G[l] = 0.0;
   const bool collide = C.inv_Kn != 0.0;
+  bool wide_wave = false;   // the correction rule lay beyond the calibrated ladder
   if (collide) {
     const double sT = sqrt(T);
     const double ub = (hw ? -u : u) * tb->inv_p0, s = sT * tb->inv_p0, y0 = -u / sT;
@@ -545,21 +546,16 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
     for (int j = 0; j < tb->nm; ++j) accum(ub + s * tb->zm[j], tb->wm[j]);
     const double ymax = wave_max(inside ? fabs(y0) : 0.0);
     if (ymax > 0.0) {
-      int li = kLadder - 1;
-      for (int j = 1; j < kLadder; ++j)
-        if (tb->lad_y[j] >= ymax) { li = j; break; }
+      const int li = ladder_entry(tb, ymax);
       const int nc = tb->lad_n[li], o = tb->lad_off[li];
       const double sgd = hw ? -1.0 : 1.0;
-      const int P = li == kLadder - 1 ? correction_panels(ymax, tb->lad_y[kLadder - 1]) : 1;
-      if (P > 1 && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
-      const double iP = 1.0 / P;   // exactly 1 for one panel
-      for (int p = 0; p < P; ++p)
-        for (int j = 0; j < nc; ++j) {
-          const double t = (p + tb->ltau[o + j]) * iP;
-          const double yt = y0 * t;
-          const double e = y0 * (tb->llamw[o + j] * iP) * exp(-0.5 * yt * yt);
-          accum(ub * (1.0 - t), -sgd * e);
-        }
+      wide_wave = nc > tb->lad_n[kLadder - 1];
+      for (int j = 0; j < nc; ++j) {
+        const double t = tb->ltau[o + j];
+        const double yt = y0 * t;
+        const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
+        accum(ub * (1.0 - t), -sgd * e);
+      }
     }
   }
 
@@ -753,6 +749,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
       if ((j * NC + fn + 1) % HHLB_SCHED_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
     }
   }
+  // waves whose correction lay beyond the calibrated ladder, counted once the
+  // registers of the step are free
+  if (wide_wave && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
 }
 
 }  // namespace hhlb

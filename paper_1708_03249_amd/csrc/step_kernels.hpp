@@ -15,8 +15,11 @@ namespace hhlb {
 
 constexpr int kQmaxDev = 16;   // largest per-half order with a kernel
 constexpr int kNc = 8;         // Gauss-Legendre points of the full-range kernel's correction
-constexpr int kLadder = 8;     // correction point counts the half-range kernel chooses from
-constexpr int kLadderPts = 64; // total points over the ladder
+constexpr int kLadder = 8;     // calibrated correction point counts the half-range kernel chooses from
+constexpr int kComposite = 6;  // beyond them: the top count on 2, 4, .., 64 panels
+constexpr int kLadderAll = kLadder + kComposite;
+constexpr int kLadderTop = 16; // the top calibrated count
+constexpr int kLadderPts = 64 + kLadderTop * (2 + 4 + 8 + 16 + 32 + 64);   // points over all entries
 constexpr int kWin = 58;       // output cells per wavefront
 
 // Build-time tuning switches of the half-range kernel: matrix cores for the
@@ -60,9 +63,11 @@ struct DevTables {
   // half-range kernel: monic recurrence q_{l+1} = (x - a_l) q_l - b_l q_{l-1}
   double mb[kQmaxDev + 2];                // b_l
   double HWs[kQmaxDev * kQmaxDev];        // H x Q: w_k h_l(z_k) / sqrt(b_0 .. b_l) (zero beyond N)
-  // correction ladder: count lad_n[j] is exact enough up to |y0| <= lad_y[j]
-  int lad_n[kLadder], lad_off[kLadder];
-  double lad_y[kLadder];
+  // correction ladder: count lad_n[j] is exact enough up to |y0| <= lad_y[j];
+  // entries kLadder.. are composite rules of the top count (2^(j-kLadder+1)
+  // panels over [y0, 0], each panel within the top count's reach)
+  int lad_n[kLadderAll], lad_off[kLadderAll];
+  double lad_y[kLadderAll];
   double ltau[kLadderPts], llamw[kLadderPts];
   // main-part rule of the equilibrium: the M-point half-range Gauss rule,
   // M = ceil((N+1)/2), exact for the degree-N integrands
@@ -124,6 +129,7 @@ struct StageArgs {
   int32_t nwin;
   int32_t stage;             // 0, 1, 2 (only stage 2 writes the wall densities)
   int32_t xcd_map;           // 1: XCD-aware block -> window mapping, 0: identity
+  int32_t nblocks;           // launch across classes: blocks (0: one per window)
   const double *inv_dx;      // per cell
   const double *gw;          // wall equilibria
   // state arrays: double (FP64 form) or float (mixed form)
@@ -319,7 +325,9 @@ __device__ __forceinline__ int xcd_window(int b, int n) {
 }
 
 // Panels of the correction integral over [y0, 0] of the half-range
-// equilibrium (the change of variables of the host builder): one while the
+// equilibrium in the node-parallel path, one cell per evaluation (the
+// change of variables of the host builder; the window kernels use the
+// tabulated composite entries of ladder_entry instead): one while the
 // largest |y0| of the wave lies within the range the ladder's top count was
 // calibrated for (ytop), else the number of equal panels of that integral
 // that keeps each one within it (a composite rule of the top count).  The
@@ -330,6 +338,18 @@ __device__ __forceinline__ int correction_panels(double ymax, double ytop) {
   if (!(ytop > 0.0) || ymax <= ytop) return 1;
   if (!(ymax < ytop * kMaxPanels)) return kMaxPanels;
   return (int)ceil(ymax / ytop);
+}
+
+// The correction rule of a wave whose largest |y0| is ymax (a scalar): the
+// first ladder entry, calibrated or composite, whose reach covers it; the
+// last (64 panels of the top count) when none does, also for a non-finite
+// ymax.  Entries beyond the calibrated ones hold more points than the top
+// count, which is how the kernels count such waves.
+__device__ __forceinline__ int ladder_entry(const DevTables *tb, double ymax) {
+  int li = kLadderAll - 1;
+  for (int j = 1; j < kLadderAll; ++j)
+    if (tb->lad_y[j] >= ymax) { li = j; break; }
+  return li;
 }
 
 // Wall density of Eq. (nplus_def): n_w = -sum_in F_k / sum_out (p_k/m) g^w_k,
@@ -581,10 +601,17 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs A) {
   }
 }
 
+// Maximum over the wave (all lanes active).  After the butterfly every lane
+// holds the same value; it is returned through the first lane as a scalar,
+// so that what depends on it (the ladder entry, the loop counts of the
+// correction) stays in scalar registers and scalar branches.
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-  return x;
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -654,31 +681,29 @@ __device__ __forceinline__ void mfma_contract16_keep(const double aM[4], const d
 // holds the Q nodes of its half for f and chi; the only coupling between the
 // halves -- moment sums, the rank-1 cross term of the force matrix and the
 // wall densities -- goes through 6 KB of LDS and one barrier.
+// LDS of one window (doubles): the moment partials of the two halves and,
+// at Q = 16, the transpose tiles of the matrix-core contractions, which the
+// partials share when HHLB_HALF_ALIAS is set (a barrier separates them).
+template <int Q>
+constexpr int half_lds_doubles() {
+  constexpr int tiles = (HHLB_MFMA && Q == 16) ? 2 * 64 * 17 : 0, parts = 2 * 6 * 64;
+  return HHLB_HALF_ALIAS ? (tiles > parts ? tiles : parts) : tiles + parts;
+}
+
+// One window of the half-range stage, run by a block of two waves (one per
+// momentum half); s_lds holds half_lds_doubles<Q>() doubles and s_nw two.
 template <int Q, int NFUN, int ADV>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_WAVES))) void stage_kernel_half(
-    StageArgs A, const DevTables *__restrict__ tb, const DevChannel *__restrict__ chans,
-    const DevWindow *__restrict__ wins, const double *__restrict__ inv_dx,
-    const double *__restrict__ gw, const double *__restrict__ in_f,
-    const double *__restrict__ in_c) {
+__device__ __forceinline__ void stage_half_window(
+    const StageArgs &A, const DevTables *__restrict__ tb, const DevChannel *__restrict__ chans,
+    const DevWindow win, const double *__restrict__ inv_dx, const double *__restrict__ gw,
+    const double *__restrict__ in_f, const double *__restrict__ in_c, double *s_lds, double *s_nw) {
   constexpr int H = Q;
   constexpr int NC = NFUN;
-  __shared__ double s_nw[2];
   constexpr bool kMfma = HHLB_MFMA && (H == 16);   // matrix cores for the 16 x 16 contractions
-#if HHLB_HALF_ALIAS
-  // the moment partials share the transpose tiles' memory (a barrier
-  // separates them)
-  constexpr int kLds = (kMfma ? 2 * 64 * 17 : 1) > 2 * 6 * 64 ? 2 * 64 * 17 : 2 * 6 * 64;
-  __shared__ double s_lds[kLds];
   double (*s_part)[6][64] = reinterpret_cast<double (*)[6][64]>(s_lds);
-  double *s_T = s_lds;
-#else
-  __shared__ double s_part[2][6][64];
-  __shared__ double s_T[kMfma ? 2 * 64 * 17 : 1];
-#endif
+  double *s_T = HHLB_HALF_ALIAS ? s_lds : s_lds + 2 * 6 * 64;
   const int hw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int w = A.xcd_map ? xcd_window(blockIdx.x, A.nwin) : (int)blockIdx.x;
-  const DevWindow win = wins[w];
   const DevChannel C = chans[win.ch];
   const int Nx = C.Nx;
   const int i = win.i0 - kHalo + lane;
@@ -798,6 +823,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
 #pragma unroll
   for (int l = 0; l < Q; ++l) G[l] = 0.0;
   const bool collide = C.inv_Kn != 0.0;
+  bool wide_wave = false;   // the correction rule lay beyond the calibrated ladder
   if (collide) {
     const double sT = sqrt(T);
     const double ub = sg * u * tb->inv_p0, s = sT * tb->inv_p0, y0 = -u / sT;
@@ -817,20 +843,15 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
     // correction over [y0, 0]: the smallest ladder entry that covers the wave
     const double ymax = wave_max(inside ? fabs(y0) : 0.0);
     if (ymax > 0.0) {
-      int li = kLadder - 1;
-      for (int j = 1; j < kLadder; ++j)
-        if (tb->lad_y[j] >= ymax) { li = j; break; }
+      const int li = ladder_entry(tb, ymax);
       const int nc = tb->lad_n[li], o = tb->lad_off[li];
-      const int P = li == kLadder - 1 ? correction_panels(ymax, tb->lad_y[kLadder - 1]) : 1;
-      if (P > 1 && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
-      const double iP = 1.0 / P;   // exactly 1 for one panel
-      for (int p = 0; p < P; ++p)
-        for (int j = 0; j < nc; ++j) {
-          const double t = (p + tb->ltau[o + j]) * iP;
-          const double yt = y0 * t;
-          const double e = y0 * (tb->llamw[o + j] * iP) * exp(-0.5 * yt * yt);
-          accum(ub * (1.0 - t), -sg * e);
-        }
+      wide_wave = nc > tb->lad_n[kLadder - 1];
+      for (int j = 0; j < nc; ++j) {
+        const double t = tb->ltau[o + j];
+        const double yt = y0 * t;
+        const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
+        accum(ub * (1.0 - t), -sg * e);
+      }
     }
   }
 
@@ -942,6 +963,61 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_W
       // interleaving more unrolled WENO evaluations exceeds the register file
       if ((j * NC + fn + 1) % HHLB_SCHED_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
     }
+  }
+  // waves whose correction lay beyond the calibrated ladder, counted once the
+  // registers of the step are free
+  if (wide_wave && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
+}
+
+template <int Q, int NFUN, int ADV>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_HALF_WAVES))) void stage_kernel_half(
+    StageArgs A, const DevTables *__restrict__ tb, const DevChannel *__restrict__ chans,
+    const DevWindow *__restrict__ wins, const double *__restrict__ inv_dx,
+    const double *__restrict__ gw, const double *__restrict__ in_f,
+    const double *__restrict__ in_c) {
+  __shared__ double s_lds[half_lds_doubles<Q>()];
+  __shared__ double s_nw[2];
+  const int w = A.xcd_map ? xcd_window(blockIdx.x, A.nwin) : (int)blockIdx.x;
+  stage_half_window<Q, NFUN, ADV>(A, tb, chans, wins[w], inv_dx, gw, in_f, in_c, s_lds, s_nw);
+}
+
+// One launch per stage for the windows of several half-range model classes
+// that share the functions and the scheme (FP64).  Record b names the window
+// and its class; the class's order Q, the same for the whole block, selects
+// the per-order window code (orders up to QTOP with a kernel of their own).
+// Persistent form: with fewer blocks than windows each block takes windows
+// b, b + gridDim.x, .. in turn.
+struct DevClassWindow {
+  int32_t ch, i0;   // as DevWindow
+  int32_t cls, Q;   // model class (index of its tables) and its order
+};
+
+template <int QTOP, int NFUN, int ADV, bool PERSIST>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(QTOP <= 8 ? 4 : HHLB_HALF_WAVES))) void stage_kernel_classes(
+    StageArgs A, const DevTables *__restrict__ tbs, const DevChannel *__restrict__ chans,
+    const DevClassWindow *__restrict__ wins, const double *__restrict__ inv_dx,
+    const double *__restrict__ gw, const double *__restrict__ in_f,
+    const double *__restrict__ in_c) {
+  __shared__ double s_lds[half_lds_doubles<QTOP>()];
+  __shared__ double s_nw[2];
+  for (int b = blockIdx.x; b < A.nwin; b += gridDim.x) {
+    if (PERSIST && b != (int)blockIdx.x) __syncthreads();   // the last window's LDS reads are done
+    const int w = A.xcd_map ? xcd_window(b, A.nwin) : b;
+    const DevClassWindow cw = wins[w];
+    const DevWindow win{cw.ch, cw.i0};
+    const DevTables *tb = tbs + __builtin_amdgcn_readfirstlane(cw.cls);
+    switch (__builtin_amdgcn_readfirstlane(cw.Q)) {
+#define HHLB_CLASS_CASE(q)                                                                   \
+  case q:                                                                                    \
+    if constexpr (q <= QTOP)                                                                 \
+      stage_half_window<q, NFUN, ADV>(A, tb, chans, win, inv_dx, gw, in_f, in_c, s_lds, s_nw); \
+    break;
+      HHLB_CLASS_CASE(1) HHLB_CLASS_CASE(2) HHLB_CLASS_CASE(3) HHLB_CLASS_CASE(4)
+      HHLB_CLASS_CASE(6) HHLB_CLASS_CASE(8) HHLB_CLASS_CASE(12) HHLB_CLASS_CASE(16)
+#undef HHLB_CLASS_CASE
+      default: break;
+    }
+    if constexpr (!PERSIST) break;   // one window per block
   }
 }
 
@@ -1105,6 +1181,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HHLB_QUARTE
   double G[Q];
 #pragma unroll
   for (int l = 0; l < Q; ++l) G[l] = 0.0;
+  bool wide_wave = false;   // the correction rule lay beyond the calibrated ladder
   if (C.inv_Kn != 0.0) {
     const double sT = sqrt(T);
     const double ub = sg * u * tb->inv_p0, s = sT * tb->inv_p0, y0 = -u / sT;
@@ -1123,20 +1200,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HHLB_QUARTE
     for (int j = 0; j < tb->nm; ++j) accum(ub + s * tb->zm[j], tb->wm[j]);
     const double ymax = wave_max(inside ? fabs(y0) : 0.0);
     if (ymax > 0.0) {
-      int li = kLadder - 1;
-      for (int j = 1; j < kLadder; ++j)
-        if (tb->lad_y[j] >= ymax) { li = j; break; }
+      const int li = ladder_entry(tb, ymax);
       const int nc = tb->lad_n[li], o = tb->lad_off[li];
-      const int P = li == kLadder - 1 ? correction_panels(ymax, tb->lad_y[kLadder - 1]) : 1;
-      if (P > 1 && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
-      const double iP = 1.0 / P;   // exactly 1 for one panel
-      for (int p = 0; p < P; ++p)
-        for (int j = 0; j < nc; ++j) {
-          const double t = (p + tb->ltau[o + j]) * iP;
-          const double yt = y0 * t;
-          const double e = y0 * (tb->llamw[o + j] * iP) * exp(-0.5 * yt * yt);
-          accum(ub * (1.0 - t), -sg * e);
-        }
+      wide_wave = nc > tb->lad_n[kLadder - 1];
+      for (int j = 0; j < nc; ++j) {
+        const double t = tb->ltau[o + j];
+        const double yt = y0 * t;
+        const double e = y0 * tb->llamw[o + j] * exp(-0.5 * yt * yt);
+        accum(ub * (1.0 - t), -sg * e);
+      }
     }
   }
 
@@ -1208,6 +1280,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HHLB_QUARTE
     if (out_lane) optr[(int64_t)j * Nx] = yn;
     if ((j + 1) % HHLB_SCHED_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
   }
+  // waves whose correction lay beyond the calibrated ladder, counted once the
+  // registers of the step are free
+  if (wide_wave && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
 }
 
 }  // namespace hhlb

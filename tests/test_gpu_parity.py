@@ -379,6 +379,28 @@ def test_batched_workload_sample():
     _check(chans, 30, perturb=0.02, seed=11, what="batched sample")
 
 
+@pytest.mark.parametrize("merge", [1, 2])
+def test_batched_sample_one_launch_across_classes(merge):
+    """The same sample, its model classes (Q = 4, 8, 12) advanced by one
+    launch per stage (merge_classes = 1: a block per window; 2: persistent
+    blocks taking windows in turn) and a graph replay, against the oracle;
+    the solver reports one launch per stage."""
+    h = H()
+    chans = _batch_sample(9)
+    s = h.Solver(chans)
+    assert s.launch_info()[0] == len({c.Q for c in chans})
+    s.set_tuning(merge_classes=merge)
+    assert s.launch_info()[0] == 1
+    for bad in (dict(merge_classes=3), dict(merge_classes=merge, class_streams=1),
+                dict(merge_classes=merge, step_fusion=1), dict(merge_classes=merge, waves_per_window=4)):
+        with pytest.raises(h.HHLBError) as e:
+            s.set_tuning(**bad)
+        assert e.value.status == -1, bad
+    s.close()
+    _check(chans, 30, perturb=0.02, seed=11, what=f"batched sample, merge_classes={merge}",
+           tuning=dict(merge_classes=merge, graph_steps=8))
+
+
 @pytest.mark.parametrize("form", ["fp64", "mixed_f32"])
 def test_launch_configurations_bit_identical(form):
     """Class streams (each model class stepping on its own stream), graph
@@ -394,6 +416,9 @@ def test_launch_configurations_bit_identical(form):
     c0 = torch.from_numpy(np.concatenate([s[1].ravel() for s in states])).cuda()
     configs = [dict(), dict(class_streams=1), dict(graph_steps=4, class_streams=1, xcd_map=0),
                dict(graph_steps=3, class_streams=0, xcd_map=1)]
+    if form == "fp64":   # one launch per stage across the classes (FP64 only)
+        configs += [dict(merge_classes=1), dict(merge_classes=2, graph_steps=4),
+                    dict(merge_classes=2, xcd_map=0)]
     outs = []
     for cfg in configs:
         s = h.Solver(chans, precision=prec)
@@ -410,9 +435,10 @@ def test_launch_configurations_bit_identical(form):
         assert np.array_equal(outs[0][1], outs[k][1]), configs[k]
     # autotune: direct launches x {one stream, class streams} x 2 mappings and
     # 16-step graphs x 2 mappings, for 2 and (FP64 form) 4 waves per window,
-    # and (FP64 form) with and without step fusion, (trial + 1) steps each;
-    # the four-wave and fused kernels round differently from the two-wave
-    # one, so the comparison solver replays the same configurations
+    # (FP64 form) with and without step fusion, and (FP64 form) the launches
+    # across classes, (trial + 1) steps each; the four-wave and fused kernels
+    # round differently from the two-wave one, so the comparison solver
+    # replays the same candidates in the same order
     s = h.Solver(chans, precision=prec)
     s.set_state(f0, c0)
     best = s.autotune(trial_steps=2)
@@ -421,12 +447,25 @@ def test_launch_configurations_bit_identical(form):
     f, c = s.get_state()
     r = h.Solver(chans, precision=prec)
     r.set_state(f0, c0)
-    for sf in ((0, 1) if form == "fp64" else (0,)):
-        for wpw in ((2, 4) if form == "fp64" else (2,)):
-            r.set_tuning(waves_per_window=wpw, step_fusion=sf)
-            r.step(6 * 3)
+    fp64 = form == "fp64"
+    n_cand = 0
+    for sf in ((0, 1) if fp64 else (0,)):
+        for wpw in ((2, 4) if fp64 else (2,)):
+            for gs in (0, 16):
+                for cs in (0, 1):
+                    for xm in (1, 0):
+                        for mg in (0, 1, 2):
+                            if cs and gs > 0:
+                                continue
+                            if mg and (not fp64 or cs or sf or wpw != 2):
+                                continue
+                            r.set_tuning(graph_steps=gs, class_streams=cs, xcd_map=xm, waves_per_window=wpw,
+                                         step_fusion=sf, merge_classes=mg)
+                            r.step(3)
+                            n_cand += 1
+    assert n_cand == (32 if fp64 else 6)
     r.set_tuning(**{k: best[k] for k in ("graph_steps", "class_streams", "xcd_map", "waves_per_window",
-                                         "step_fusion")})
+                                         "step_fusion", "merge_classes")})
     r.step(1)
     fr, cr = r.get_state()
     torch.cuda.synchronize()
