@@ -548,6 +548,36 @@ def run_ballistic(H, torch, np, nx=24, steps=2000, warmup=32):
             "ms_per_step": ms / steps, "steps": steps}
 
 
+def run_small(H, torch, np, steps=20000, warmup=64):
+    """The small channel of the parity tests, HHLB(3;4), Nx = 64, third-order
+    upwind, f and chi, Kn = 0.1, g = -0.1, equal walls, dt = 5e-4, from the
+    equilibrium: 20 000 steps (t = 10) as 64-step HIP graphs, per-stage
+    launches and fused steps.  One channel of two windows is launch-bound:
+    this is the latency of a step.  HIP events on the solver's stream."""
+    ch = H.Channel(quad=H.HALF_HERMITE, Q=4, N=3, Nx=64, adv=H.UPWIND3, transverse_dof=2, Kn=0.1,
+                   g=-0.1, dt=5e-4)
+    rec = {"workload": "HHLB(3;4) V=8, one channel, Nx=64 uniform, upwind-3+RK3, f and chi, Kn=0.1, "
+                       "g=-0.1, equal walls, dt=5e-4, 64-step HIP graphs", "steps": steps}
+    for name, fusion in (("per_stage", 0), ("fused", 1)):
+        s = H.Solver([ch])
+        s.set_tuning(graph_steps=64, step_fusion=fusion)
+        s.init_equilibrium()
+        s.step(warmup)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s.stream)
+        s.step(steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        _, _, bad = s.diagnostics()
+        assert int(bad.item()) == 0, "small channel: non-finite populations"
+        s.close()
+        rec[name] = {"value": ch.V * ch.Nx * steps / (ms / 1e3), "unit": "node-updates/s",
+                     "us_per_step": 1e3 * ms / steps}
+    return rec
+
+
 def run_multi(H, torch, np, npts=1_000_000, steps=10, warmup=2):
     """The mixed-quadrature velocity space of App. A (homogeneous gas): a
     3-D product set HH(4) x H(4) x H(4) (V = 8 x 4 x 4 = 128, N = 3 per
@@ -624,6 +654,8 @@ def main():
     ap.add_argument("--max-steps", type=int, default=3_000_000)
     ap.add_argument("--no-ballistic", action="store_true",
                     help="skip the HHLB(20;200) ballistic record (the node-parallel path)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small-channel latency record (HHLB(3;4), Nx=64)")
     ap.add_argument("--no-multi", action="store_true",
                     help="skip the mixed-quadrature (App. A) record")
     ap.add_argument("--multi-only", action="store_true",
@@ -731,6 +763,9 @@ def main():
                         f"(Q=16, V=32, p0={LAGUERRE_P0}), FP64",
             "value": r["value"], "unit": "node-updates/s", "ms_per_step": r["ms_per_step"],
             "mass_drift": r["mass_drift"], "avg_launch_us": r["roofline"]["avg_launch_us"]}
+    if not args.no_small:
+        print("[bench] small channel HHLB(3;4), Nx=64: 20000 steps", file=sys.stderr, flush=True)
+        out["small_channel"] = run_small(H, torch, np)
     if not args.no_ballistic:
         print("[bench] ballistic HHLB(20;200): 8 channels x Nx=24", file=sys.stderr, flush=True)
         out["ballistic_q200"] = run_ballistic(H, torch, np, nx=args.ballistic_nx,
