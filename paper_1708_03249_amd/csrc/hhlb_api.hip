@@ -457,6 +457,37 @@ void fused_windows(int ch, int Nx, std::vector<hhlb::DevFusedWindow> &w) {
 }
 
 // Device tables of one model class (quadrature, Q, N, p0).
+// Correction rules beyond the calibrated ladder (entries kLadder..): the top
+// count on 2, 4, .., 64 equal panels of [y0, 0], each panel within the top
+// count's reach, so the composite rule reaches that many times as far (the
+// nodes (p + tau_q)/P, the weights lambda_q/P), tabulated after the
+// calibrated points from offset o.  Without a calibrated top reach the
+// entries repeat the top one.  T is DevTables or DevLarge.
+template <class T>
+void add_composite_entries(T &d, int o, double ytop, long double inv_s2pi) {
+  static_assert(hhlb::kLadderTop * (2 + 4 + 8 + 16 + 32 + 64) + 64 <= hhlb::kLadderPts, "ladder points");
+  std::vector<long double> tt, lt;
+  hhlb::gauss_legendre01(hhlb::kLadderTop, tt, lt);
+  for (int c = 0; c < hhlb::kComposite; ++c) {
+    const int j = hhlb::kLadder + c, P = 2 << c;
+    if (!(ytop > 0.0)) {
+      d.lad_n[j] = d.lad_n[hhlb::kLadder - 1];
+      d.lad_off[j] = d.lad_off[hhlb::kLadder - 1];
+      d.lad_y[j] = ytop;
+      continue;
+    }
+    d.lad_n[j] = hhlb::kLadderTop * P;
+    d.lad_off[j] = o;
+    d.lad_y[j] = ytop * P;
+    for (int pnl = 0; pnl < P; ++pnl)
+      for (int q = 0; q < hhlb::kLadderTop; ++q) {
+        d.ltau[o + pnl * hhlb::kLadderTop + q] = (double)((pnl + tt[q]) / P);
+        d.llamw[o + pnl * hhlb::kLadderTop + q] = (double)(lt[q] / P * inv_s2pi);
+      }
+    o += hhlb::kLadderTop * P;
+  }
+}
+
 hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb::Rule &r, hhlb::DevTables &d) {
   std::memset(&d, 0, sizeof(d));
   for (int k = 0; k < r.V; ++k) d.p[k] = r.p[k];
@@ -576,32 +607,7 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
     }
     o += counts[j];
   }
-  // beyond the calibrated reach: the top count on 2, 4, .., 64 equal panels of
-  // [y0, 0], each panel within the top count's reach, so the composite rule
-  // reaches that many times as far (the nodes (p + tau_q)/P, the weights
-  // lambda_q/P).  Without a calibrated top reach the entries repeat the top.
-  static_assert(hhlb::kLadderTop == counts[hhlb::kLadder - 1], "top ladder count");
-  const double ytop = limits[hhlb::kLadder - 1];
-  std::vector<long double> tt, lt;
-  hhlb::gauss_legendre01(hhlb::kLadderTop, tt, lt);
-  for (int c = 0; c < hhlb::kComposite; ++c) {
-    const int j = hhlb::kLadder + c, P = 2 << c;
-    if (!(ytop > 0.0)) {
-      d.lad_n[j] = d.lad_n[hhlb::kLadder - 1];
-      d.lad_off[j] = d.lad_off[hhlb::kLadder - 1];
-      d.lad_y[j] = ytop;
-      continue;
-    }
-    d.lad_n[j] = hhlb::kLadderTop * P;
-    d.lad_off[j] = o;
-    d.lad_y[j] = ytop * P;
-    for (int pnl = 0; pnl < P; ++pnl)
-      for (int q = 0; q < hhlb::kLadderTop; ++q) {
-        d.ltau[o + pnl * hhlb::kLadderTop + q] = (double)((pnl + tt[q]) / P);
-        d.llamw[o + pnl * hhlb::kLadderTop + q] = (double)(lt[q] / P * inv_s2pi);
-      }
-    o += hhlb::kLadderTop * P;
-  }
+  add_composite_entries(d, o, limits[hhlb::kLadder - 1], inv_s2pi);
   return HHLB_OK;
 }
 
@@ -680,7 +686,8 @@ hhlb_status make_large_tables(const hhlb_channel &h, int N, const hhlb::Rule &r,
   if (st2) return fail(st2, "equilibrium rule: " + err2);
   L.nm = M;
   for (int j = 0; j < M; ++j) { L.zm[j] = (double)rm.z[j]; L.wm[j] = (double)rm.w[j]; }
-  const int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
+  static constexpr int counts[hhlb::kLadder] = {0, 2, 3, 4, 6, 8, 12, 16};
+  static_assert(hhlb::kLadderTop == counts[hhlb::kLadder - 1], "top ladder count");
   double limits[hhlb::kLadder] = {0};
   hhlb::correction_limits(r, N, counts, hhlb::kLadder, 3e-16, limits);
   const long double inv_s2pi = 1.0L / sqrtl(2 * 3.141592653589793238462643383279502884L);
@@ -699,6 +706,7 @@ hhlb_status make_large_tables(const hhlb_channel &h, int N, const hhlb::Rule &r,
     }
     o += counts[j];
   }
+  add_composite_entries(L, o, limits[hhlb::kLadder - 1], inv_s2pi);
   return HHLB_OK;
 }
 

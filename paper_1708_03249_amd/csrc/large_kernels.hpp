@@ -37,8 +37,8 @@ struct DevLarge {
   double ka[kQmaxLarge], kb[kQmaxLarge];
   double a[kNmaxLarge + 2], mb[kNmaxLarge + 2];   // monic recurrence
   double zm[kQmaxDev], wm[kQmaxDev];               // main rule (half-range Gauss-Hermite)
-  int32_t lad_n[kLadder], lad_off[kLadder];
-  double lad_y[kLadder];
+  int32_t lad_n[kLadderAll], lad_off[kLadderAll];   // calibrated entries, then composite ones
+  double lad_y[kLadderAll];
   double ltau[kLadderPts], llamw[kLadderPts];
 };
 
@@ -76,10 +76,11 @@ __device__ __forceinline__ double seg_sum(double x) {
 // collected by segment sums; for the full range the closed-form recurrence
 // of Sec. IV.A.3.  Called by every lane of the wave; W >= 16 holds the main
 // rule (at most 11 points for N <= 20) and the largest correction (16).
-// NM bounds the order N (the register arrays' size).  Returns the number of
-// correction panels used (more than one beyond the ladder's calibrated range).
+// NM bounds the order N (the register arrays' size).  Returns whether the
+// correction took a composite rule (|y0| beyond the ladder's calibrated
+// range).
 template <int W = 64, int NM = kNmaxLarge>
-__device__ __forceinline__ int axis_coeffs(const DevLarge *tl, double u, double T, int lane,
+__device__ __forceinline__ bool axis_coeffs(const DevLarge *tl, double u, double T, int lane,
                                             double (&Gp)[NM + 1], double (&Gm)[NM + 1]) {
   const int N = tl->N;
 #pragma unroll
@@ -97,7 +98,7 @@ __device__ __forceinline__ int axis_coeffs(const DevLarge *tl, double u, double 
       if (l + 1 <= N) Gp[l + 1] = (ub * Gp[l] + tl->sq[l] * aa * Gp[l - 1]) / tl->sq[l + 1];
 #pragma unroll
     for (int l = 0; l <= NM; ++l) Gm[l] = (l & 1) ? -Gp[l] : Gp[l];
-    return 1;
+    return false;
   }
   const double sT = sqrt(T), s = sT * tl->inv_p0, y0 = -u / sT;
   auto accum = [&](double (&G)[NM + 1], double x, double wt) {
@@ -119,22 +120,26 @@ __device__ __forceinline__ int axis_coeffs(const DevLarge *tl, double u, double 
     accum(Gm, -u * tl->inv_p0 + s * tl->zm[lane], tl->wm[lane]);
   }
   const double ymax = fabs(y0);
-  int P = 1;
+  bool wide = false;
   if (ymax > 0.0) {
-    int li = kLadder - 1;
-    for (int j = 1; j < kLadder; ++j)
+    // the first entry, calibrated or composite, whose reach covers |y0|
+    // (the last when none does, also for a non-finite |y0|)
+    int li = kLadderAll - 1;
+    for (int j = 1; j < kLadderAll; ++j)
       if (tl->lad_y[j] >= ymax) { li = j; break; }
     const int nc = tl->lad_n[li], o = tl->lad_off[li];
-    // beyond the top count's calibrated range: equal panels of the top count
-    if (li == kLadder - 1) P = correction_panels(ymax, tl->lad_y[kLadder - 1]);
-    const double iP = 1.0 / P;   // exactly 1 for one panel
-    // nc <= 16 <= W: the segment's lanes take the points panel by panel
-    for (int q = lane; q < P * nc; q += W) {
-      const int p = q / nc, j = q - p * nc;
-      const double t = (p + tl->ltau[o + j]) * iP, yt = y0 * t;
-      const double e = y0 * (tl->llamw[o + j] * iP) * exp(-0.5 * yt * yt);
-      accum(Gp, u * tl->inv_p0 * (1.0 - t), -e);
-      accum(Gm, -u * tl->inv_p0 * (1.0 - t), e);
+    wide = nc > tl->lad_n[kLadder - 1];
+    // the segment's lanes take the entry's points in rounds of W: one round
+    // for a calibrated count (nc <= 16 <= W), more for a composite rule
+    const int rounds = (nc + W - 1) / W;
+    for (int rr = 0; rr < rounds; ++rr) {
+      const int q = rr * W + lane;
+      if (q < nc) {
+        const double t = tl->ltau[o + q], yt = y0 * t;
+        const double e = y0 * tl->llamw[o + q] * exp(-0.5 * yt * yt);
+        accum(Gp, u * tl->inv_p0 * (1.0 - t), -e);
+        accum(Gm, -u * tl->inv_p0 * (1.0 - t), e);
+      }
     }
   }
 #pragma unroll
@@ -144,7 +149,7 @@ __device__ __forceinline__ int axis_coeffs(const DevLarge *tl, double u, double 
       Gm[l] = seg_sum<W>(Gm[l]);
     }
   }
-  return P;
+  return wide;
 }
 
 // Cell phase: a 1-D grid of nwin x (kCellGroups + 1) blocks; block b maps to
@@ -210,8 +215,8 @@ __global__ __launch_bounds__(256) void large_cell_kernel(LargeArgs A) {
 #pragma unroll
     for (int l = 0; l <= kNmaxLarge; ++l) Gp[l] = Gm[l] = 0.0;
     if (C.inv_Kn != 0.0) {
-      const int P = axis_coeffs(tl, u, T, lane, Gp, Gm);
-      if (P > 1 && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
+      const bool wide = axis_coeffs(tl, u, T, lane, Gp, Gm);
+      if (wide && lane == 0 && A.wide) atomicAdd(A.wide, 1ull);
     }
     if (lane == 0) {
       double *out = A.cell + (int64_t)(C.cell_off + i) * kCellStride;

@@ -324,22 +324,6 @@ __device__ __forceinline__ int xcd_window(int b, int n) {
   return x * q + (x < r ? x : r) + pos;
 }
 
-// Panels of the correction integral over [y0, 0] of the half-range
-// equilibrium in the node-parallel path, one cell per evaluation (the
-// change of variables of the host builder; the window kernels use the
-// tabulated composite entries of ladder_entry instead): one while the
-// largest |y0| of the wave lies within the range the ladder's top count was
-// calibrated for (ytop), else the number of equal panels of that integral
-// that keeps each one within it (a composite rule of the top count).  The
-// count is capped at kMaxPanels, which also covers non-finite |y0|.  A ladder
-// without a calibrated top count (ytop <= 0) keeps one panel.
-constexpr int kMaxPanels = 64;
-__device__ __forceinline__ int correction_panels(double ymax, double ytop) {
-  if (!(ytop > 0.0) || ymax <= ytop) return 1;
-  if (!(ymax < ytop * kMaxPanels)) return kMaxPanels;
-  return (int)ceil(ymax / ytop);
-}
-
 // The correction rule of a wave whose largest |y0| is ymax (a scalar): the
 // first ladder entry, calibrated or composite, whose reach covers it; the
 // last (64 panels of the top count) when none does, also for a non-finite
