@@ -120,7 +120,7 @@ def tables(quad: int, Q: int, p0: float = 1.0):
 
 def set_qmono(qmono: int) -> int:
     """Test-only: half-range Hermite rules with Q > qmono are built from the
-    three-term recurrence instead of monomial coefficients (default 32).
+    three-term recurrence instead of monomial coefficients (default 16).
     Returns the previous value."""
     return lib().orc_set_qmono(int(qmono))
 
