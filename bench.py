@@ -449,6 +449,28 @@ def cpu_baseline(H, torch, np, forms, steps, n_parity=4, max_threads=16):
     return out
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Bandwidth a plain device copy of mib MiB reaches on this GPU (read +
+    write bytes over the copy time, best of reps): the practical ceiling the
+    stage kernels' HBM fraction is also quoted against."""
+    n = mib * 2**20 // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / (best / 1e3) / 1e9
+
+
 def run_form(H, torch, np, chans, form, args):
     """Warm up, time args.steps steps of one arithmetic form; return its
     record and the final moments (device tensors)."""
@@ -725,6 +747,10 @@ def main():
         del mom
         torch.cuda.empty_cache()
     prim = results[forms[0]]
+    copy_gbs = copy_bandwidth(torch)
+    for r in results.values():
+        r["roofline"]["copy_GBps"] = round(copy_gbs, 1)
+        r["roofline"]["frac_of_copy"] = round(r["roofline"]["achieved"] / copy_gbs, 4)
     out = {
         "metric": "velocity-node updates/s (x·p_x)",
         "value": prim["value"],
