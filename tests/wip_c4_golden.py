@@ -1,0 +1,100 @@
+"""The batched workload's deterministic subset against a stored oracle
+result: every 16th of the 4096 channels (256 channels of uneven Nx, Q in
+{4, 8, 12}, Kn from 1e-3 to 10, dt = min(CFL 0.5, Kn/2)) in one solver,
+1000 RK-3 steps from the modulated equilibrium that
+tests/golden/make_c4_golden.py (oracle only) advanced to write
+tests/golden/c4_every16th_1000.npz.  Every channel's n, u, T are compared
+with the oracle's: within 1e-12 for the FP64 form (per-class launches and
+the one launch across classes), within 1e-5 for the mixed forms."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_common import to_oracle  # noqa: E402
+
+import oracle as O  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "c4_every16th_1000.npz")
+AMP = 0.05
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def case():
+    """Channels, the oracle's start (the stored result's own recipe) and the
+    stored result."""
+    import paper_1708_03249_amd as H
+    from paper_1708_03249_amd.inputs import batch_draws, smooth_modulation
+    g = np.load(GOLDEN)
+    draws = batch_draws(4096, 0)
+    idx = [int(k) for k in g["idx"]]
+    chans = [H.Channel(quad=H.HALF_HERMITE, Q=draws[k]["Q"], N=draws[k]["Q"] - 1, Nx=draws[k]["Nx"],
+                       adv=H.WENO5, transverse_dof=2, stretch_A=0.0, Kn=draws[k]["Kn"], g=draws[k]["g"],
+                       T_right=draws[k]["T_right"], dt=-0.5) for k in idx]
+    f0, c0 = [], []
+    for k, ch in zip(idx, chans):
+        f, chi = O.initial_state(to_oracle(ch))
+        V = f.shape[0]
+        f0.append((f * smooth_modulation(2 * k, V, ch.Nx, AMP)).ravel())
+        c0.append((chi * smooth_modulation(2 * k + 1, V, ch.Nx, AMP)).ravel())
+    return chans, np.concatenate(f0), np.concatenate(c0), g
+
+
+def _errors(chans, cells, n, u, T, g):
+    en = eu = eT = 0.0
+    worst = (0.0, -1)
+    for c, ch in enumerate(chans):
+        a0, a1 = int(cells[c]), int(cells[c + 1])
+        rn, ru, rT = g["n"][a0:a1], g["u"][a0:a1], g["T"][a0:a1]
+        e = (np.abs(n[a0:a1] - rn).max() / rn.max(), np.abs(u[a0:a1] - ru).max() / math.sqrt(ch.T_left),
+             np.abs(T[a0:a1] - rT).max() / rT.max())
+        en, eu, eT = max(en, e[0]), max(eu, e[1]), max(eT, e[2])
+        worst = max(worst, (max(e), c))
+    return en, eu, eT, worst
+
+
+@pytest.mark.parametrize("form,tuning,tol", [
+    ("fp64", {}, 1e-12),
+    ("fp64", {"merge_classes": 1, "graph_steps": 16}, 1e-12),
+    ("mixed_f32", {}, 1e-5),
+    ("mixed_bf16", {}, 1e-5),
+    ("mixed_f16", {}, 1e-5),
+])
+def test_batched_subset_1000_steps_against_stored_oracle(case, form, tuning, tol):
+    import torch
+    import paper_1708_03249_amd as H
+    chans, f0, c0, g = case
+    steps = int(g["steps"])
+    s = H.Solver(chans, precision=H.PRECISIONS[form])
+    try:
+        # the library resolves the same CFL / Kn rule as the oracle (to two ulps)
+        assert np.all(np.abs(s.dt - g["dt"]) <= 4.5e-16 * g["dt"]), "time steps differ from the oracle's"
+        assert np.array_equal(np.diff(s.cells), g["Nx"])
+        if tuning:
+            s.set_tuning(**tuning)
+        s.set_state(torch.from_numpy(f0).cuda(), torch.from_numpy(c0).cuda())
+        print(f"[c4] {form} {tuning}: {len(chans)} channels, {steps} steps", flush=True)
+        s.step(steps)
+        n, u, T = (a.cpu().numpy() for a in s.moments())
+        _, _, bad = s.diagnostics()
+        assert int(bad.cpu().item()) == 0
+        cells = s.cells
+    finally:
+        s.close()
+    en, eu, eT, (ew, wc) = _errors(chans, cells, n, u, T, g)
+    print(f"[c4] {form}: err n {en:.2e} u {eu:.2e} T {eT:.2e}; worst channel {int(g['idx'][wc])} "
+          f"(Q={chans[wc].Q}, Nx={chans[wc].Nx}, Kn={chans[wc].Kn:.3g})", flush=True)
+    assert max(en, eu, eT) <= tol, (en, eu, eT, int(g["idx"][wc]))
