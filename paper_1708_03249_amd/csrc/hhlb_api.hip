@@ -577,9 +577,11 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
           kh = round_bf16(d.Ks[k * r.H + j]);
           kl = round_bf16(d.Ks[k * r.H + j] - kh);
         } else if (precision == HHLB_MIXED_F16) {
+          // the low part as the kernel forms it: the remainder rounded to
+          // FP16 at 2^11 times its size, then scaled back (exact)
           const float x = d.Ks16[k * r.H + j], xh = round_f16(x);
           kh = xh * d.irsc[k];
-          kl = round_f16(x - xh) * d.irsc[k];
+          kl = round_f16((x - xh) * 2048.0f) / 2048.0f * d.irsc[k];
         }
         c += r.w[k] * (long double)kh;
         cl += r.w[k] * (long double)kl;

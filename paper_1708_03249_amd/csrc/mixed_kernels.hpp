@@ -36,7 +36,7 @@
 #define HHLB_MIXED_ALIAS 1
 #endif
 #ifndef HHLB_PREFETCH_MIXED
-#define HHLB_PREFETCH_MIXED 6
+#define HHLB_PREFETCH_MIXED 10
 #endif
 #ifndef HHLB_MIXED_WAVES
 #define HHLB_MIXED_WAVES 4
@@ -236,6 +236,20 @@ __device__ __forceinline__ float operand_value(float x) {
   else return x;
 }
 
+// FP16 low parts are formed 2^11 times larger than the remainder they stand
+// for: the remainder of an entry below FP16's normal range (2^-14) would
+// otherwise fall into its subnormals, which keep only an absolute 2^-24.
+// The products of the low parts are scaled back in FP32 before the product
+// of the high parts is added.  BF16 has the FP32 exponent range: no scale.
+constexpr float kF16LoScale = 2048.0f, kF16LoUnscale = 1.0f / 2048.0f;
+
+// The value the matrix cores see for the low part of x (x = xh + remainder).
+template <int PREC>
+__device__ __forceinline__ float low_value(float x, float xh) {
+  if constexpr (PREC == kPrecF16) return (float)(_Float16)((x - xh) * kF16LoScale) * kF16LoUnscale;
+  else return operand_value<PREC>(x - xh);
+}
+
 // A operand of the force block for the matrix cores, built once per wave
 // from the FP32 table Ks (H x H, row-major), zero outside the H x H block.
 // Register layouts (checked on the GPU):
@@ -287,7 +301,7 @@ struct ForceA<kPrecF16> {   // loaded from the row-scaled table Ks16
       const int k = 4 * (lane >> 4) + t;
       const float x = (i < H && k < H) ? Ks[(i < H ? i : 0) * H + (k < H ? k : 0)] : 0.0f;
       v[t] = (_Float16)x;
-      lo[t] = (_Float16)(x - (float)v[t]);
+      lo[t] = (_Float16)((x - (float)v[t]) * kF16LoScale);
     }
   }
 };
@@ -324,7 +338,7 @@ __device__ __forceinline__ void mfma_force(const ForceA<PREC> &aM, const float X
       }
       // hi/lo split of both operands: Kh yh + Kh yl + Kl yh, the small
       // products first (the dropped Kl yl is below 2^-16 of |K||y| in BF16,
-      // 2^-22 in FP16)
+      // 2^-22 in FP16; the FP16 low parts come scaled by kF16LoScale)
       if constexpr (PREC == kPrecBF16) {
         bfx4 bh, bl;
 #pragma unroll
@@ -340,10 +354,12 @@ __device__ __forceinline__ void mfma_force(const ForceA<PREC> &aM, const float X
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           bh[t] = (_Float16)bv[t];
-          bl[t] = (_Float16)(bv[t] - (float)bh[t]);
+          bl[t] = (_Float16)((bv[t] - (float)bh[t]) * kF16LoScale);
         }
         acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(aM.lo, bh, acc[cb], 0, 0, 0);
         acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(aM.v, bl, acc[cb], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[cb][r] *= kF16LoUnscale;   // exact: a power of two
         acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(aM.v, bh, acc[cb], 0, 0, 0);
       }
     }
@@ -630,7 +646,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(HHLB_MIXED_
 #pragma unroll
           for (int j = 0; j < H; ++j) {
             ys[j] = y[j] * sc;
-            const float yh = operand_value<PREC>(ys[j]), yl = operand_value<PREC>(ys[j] - yh);
+            const float yh = operand_value<PREC>(ys[j]), yl = low_value<PREC>(ys[j], yh);
             d = fmaf(tb->crs[j], yh + yl, fmaf(tb->crs_lo[j], yh, d));
           }
           mfma_force<PREC, H>(aK, ys, ky, Tw, lane);
