@@ -129,10 +129,10 @@ __device__ __forceinline__ bool axis_coeffs(const DevLarge *tl, double u, double
       if (tl->lad_y[j] >= ymax) { li = j; break; }
     const int nc = tl->lad_n[li], o = tl->lad_off[li];
     wide = nc > tl->lad_n[kLadder - 1];
-    // the segment's lanes take the entry's points in rounds of W: one round
+    // the segment's lanes take the entry's points W at a time: one pass
     // for a calibrated count (nc <= 16 <= W), more for a composite rule
-    const int rounds = (nc + W - 1) / W;
-    for (int rr = 0; rr < rounds; ++rr) {
+    const int passes = (nc + W - 1) / W;
+    for (int rr = 0; rr < passes; ++rr) {
       const int q = rr * W + lane;
       if (q < nc) {
         const double t = tl->ltau[o + q], yt = y0 * t;
