@@ -182,9 +182,14 @@ def run_batch(H, torch, np, args):
         torch.cuda.synchronize()
         assert int(bad.item()) == 0, f"batch {name}: non-finite populations"
         used.pop("ms_per_step", None)
+        # algorithmic HBM bytes of a step over its time (every class together)
+        bform = "fp64_fused" if tuning.get("step_fusion") else form
+        gbs = bytes_per_node_update(bform) * nu_step / (ms / args.batch_steps / 1e3) / 1e9
         rec = {"value": nu_step * args.batch_steps / (ms / 1e3), "unit": "node-updates/s",
                "ms_per_step": ms / args.batch_steps, "tuning": used,
                "launches_per_stage": s.launch_info()[0],
+               "hbm": {"algorithmic_bytes_per_node_update": bytes_per_node_update(bform),
+                       "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)},
                "mass_drift": float(((mass - mass0) / mass0).abs().max().item())}
         if name == "fp64":
             ref = mom
