@@ -45,6 +45,7 @@ const hhlb::LaunchMap &launchers() {
   static hhlb::LaunchMap m = [] {
     hhlb::LaunchMap t;
     hhlb::register_fp64(t);
+    hhlb::register_fp64_q16(t);
     hhlb::register_mixed_f32(t);
     hhlb::register_mixed_bf16(t);
     hhlb::register_mixed_f16(t);

@@ -19,6 +19,7 @@ using LaunchKey = std::tuple<int, int, int, int, int, int>;
 using LaunchMap = std::map<LaunchKey, Launcher>;
 
 void register_fp64(LaunchMap &m);
+void register_fp64_q16(LaunchMap &m);
 void register_mixed_f32(LaunchMap &m);
 void register_mixed_bf16(LaunchMap &m);
 void register_mixed_f16(LaunchMap &m);
