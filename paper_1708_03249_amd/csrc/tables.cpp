@@ -14,6 +14,9 @@
 
 #include <cfloat>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "../../include/hhlb.h"
 
@@ -119,7 +122,7 @@ void jacobi_eigenvalues(const Rule &r, int n, ld lo, ld hi, std::vector<ld> &ev)
 
 }  // namespace
 
-void gauss_legendre01(int n, std::vector<ld> &tau, std::vector<ld> &lam) {
+static void compute_gauss_legendre01(int n, std::vector<ld> &tau, std::vector<ld> &lam) {
   tau.resize(n);
   lam.resize(n);
   for (int i = 0; i < n; ++i) {
@@ -141,6 +144,26 @@ void gauss_legendre01(int n, std::vector<ld> &tau, std::vector<ld> &lam) {
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j)
       if (tau[j] < tau[i]) { std::swap(tau[i], tau[j]); std::swap(lam[i], lam[j]); }
+}
+
+// The rules are built once per point count and process: the equilibrium's
+// correction-ladder calibration asks for the same few counts thousands of
+// times.
+void gauss_legendre01(int n, std::vector<ld> &tau, std::vector<ld> &lam) {
+  static std::mutex mu;
+  static std::map<int, std::pair<std::vector<ld>, std::vector<ld>>> memo;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = memo.find(n);
+    if (it != memo.end()) {
+      tau = it->second.first;
+      lam = it->second.second;
+      return;
+    }
+  }
+  compute_gauss_legendre01(n, tau, lam);
+  std::lock_guard<std::mutex> lock(mu);
+  memo.emplace(n, std::make_pair(tau, lam));
 }
 
 int build_rule(int quad, int Q, double p0, Rule &r, std::string &err) {
