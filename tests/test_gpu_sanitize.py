@@ -23,9 +23,16 @@ def test_solver_lifecycle_under_host_sanitizers():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    src = os.path.join(HERE, "sanitize", "solver_lifecycle.cpp")
-    if not (os.path.exists(EXE) and os.path.exists(CHANNELS)) or os.path.getmtime(EXE) < os.path.getmtime(src):
+    if not (os.path.exists(EXE) and os.path.exists(CHANNELS)):
         pytest.skip("sanitized driver not built (python tests/sanitize/build_sanitized.py)")
+    root = os.path.dirname(HERE)
+    csrc = os.path.join(root, "paper_1708_03249_amd", "csrc")
+    sources = [os.path.join(HERE, "sanitize", "solver_lifecycle.cpp"), os.path.join(root, "include", "hhlb.h")]
+    sources += [os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp", ".cpp", ".h"))]
+    stale = [f for f in sources if os.path.getmtime(f) > os.path.getmtime(EXE)]
+    if stale:
+        pytest.skip(f"sanitized driver older than {os.path.basename(stale[0])}: rebuild it "
+                    "(python tests/sanitize/build_sanitized.py)")
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
     print(f"[sanitize] {EXE} gpu {CHANNELS}", flush=True)
