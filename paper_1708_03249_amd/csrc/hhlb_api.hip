@@ -615,8 +615,9 @@ hhlb_status make_tables(const hhlb_channel &h, int N, int precision, const hhlb:
 }
 
 // The device tables of a model class, built once per process: the
-// correction-ladder calibration alone takes seconds, and solvers (e.g. one
-// per channel) often repeat the same classes.
+// correction-ladder calibration evaluates the equilibrium thousands of times
+// (about 0.1 s per class), and solvers (e.g. one per channel) often repeat
+// the same classes.
 hhlb_status cached_tables(const hhlb_channel &h, int N, int precision, const hhlb::Rule &r, hhlb::DevTables &d) {
   using Key = std::tuple<int, int, int, double, int>;
   static std::mutex mu;
