@@ -401,6 +401,44 @@ def test_batched_sample_one_launch_across_classes(merge):
            tuning=dict(merge_classes=merge, graph_steps=8))
 
 
+@pytest.mark.parametrize("merge", [1, 2])
+def test_one_launch_across_classes_every_group_shape(merge):
+    """Launch groups other than the batch's: Q = 16, 12 and 4 with a
+    half-range Gauss-Laguerre Q = 8 class (f and chi, WENO-5; the kernel for
+    orders up to 16), and Q = 2 and 6 (f only, upwind-3; up to 8), beside a
+    full-range channel that keeps its own launch.  The merged launches (and
+    graph replay) give the bits of the per-class launches, and the oracle's
+    result within the FP64 tolerance."""
+    h = H()
+    chans = [
+        h.Channel(quad=h.HALF_HERMITE, Q=16, Nx=70, adv=h.WENO5, stretch_A=0.9, T_right=1.4, g=-0.5,
+                  Kn=0.05, dt=-0.5),
+        h.Channel(quad=h.HALF_HERMITE, Q=4, Nx=90, adv=h.WENO5, T_right=1.2, g=-0.2, Kn=0.2, dt=-0.5),
+        h.Channel(quad=h.HALF_HERMITE, Q=12, Nx=64, adv=h.WENO5, stretch_A=0.5, g=-1.0, Kn=0.02, dt=-0.5),
+        h.Channel(quad=h.HALF_LAGUERRE, Q=8, N=4, Nx=61, adv=h.WENO5, p0=0.3, T_right=1.3, g=-0.3, Kn=0.1,
+                  dt=-0.5),
+        h.Channel(quad=h.HALF_HERMITE, Q=2, Nx=40, adv=h.UPWIND3, transverse_dof=0, g=-0.3, Kn=0.1, dt=-0.5),
+        h.Channel(quad=h.HALF_HERMITE, Q=6, Nx=75, adv=h.UPWIND3, transverse_dof=0, T_right=1.6, Kn=1.0,
+                  dt=-0.5),
+        h.Channel(quad=h.FULL_HERMITE, Q=8, Nx=50, adv=h.WENO5, T_right=1.3, g=-0.4, Kn=0.1, dt=-0.5),
+    ]
+    s = h.Solver(chans)
+    assert s.launch_info()[0] == 7
+    s.set_tuning(merge_classes=merge)
+    assert s.launch_info()[0] == 3   # two launch groups and the full-range class
+    s.close()
+    nsteps = 20
+    print(f"[parity] launch groups, merge_classes={merge}: {len(chans)} channels, {nsteps} steps", flush=True)
+    states = initial_states(chans, seed=5, perturb=0.02)
+    base = run_gpu(chans, states, nsteps)
+    merged = run_gpu(chans, states, nsteps, tuning=dict(merge_classes=merge, graph_steps=8))
+    assert base["bad"] == 0 and merged["bad"] == 0
+    for key in ("f", "chi", "n", "u", "T", "nw"):
+        assert np.array_equal(base[key], merged[key]), key
+    ref = run_oracle(chans, states, nsteps, merged["dt"])
+    compare(chans, merged, ref, tol=TOL, what=f"launch groups, merge_classes={merge}")
+
+
 @pytest.mark.parametrize("form", ["fp64", "mixed_f32"])
 def test_launch_configurations_bit_identical(form):
     """Class streams (each model class stepping on its own stream), graph
