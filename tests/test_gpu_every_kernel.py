@@ -7,8 +7,10 @@ one solver, so that each model class runs its own kernel.  The solvers run
 4 RK-3 steps from a perturbed equilibrium (Nx = 64..119, so two windows with
 a ragged second one; half of the channels on the stretched grid) in every
 launch option that selects other kernels: the two-wave stage kernels, the
-four-wave ones (f and chi), the fused step, and each mixed form.  FP64 is
-held to 1e-12 of the oracle, the mixed forms to 1e-5."""
+four-wave ones (f and chi), the fused step, each mixed form, and the
+launches across classes (for orders up to 8, 12 and 16, a block per window
+or persistent).  FP64 is held to 1e-12 of the oracle, the mixed forms to
+1e-5."""
 import math
 import os
 import sys
@@ -71,3 +73,16 @@ def test_every_full_range_fp64_kernel():
 def test_every_mixed_kernel(form):
     import paper_1708_03249_amd as H
     _run(_shapes(H.HALF_HERMITE, HALF_ORDERS), H.PRECISIONS[form], None, 1e-5, form)
+
+
+@pytest.mark.parametrize("merge", [1, 2])
+@pytest.mark.parametrize("top", [8, 12, 16])
+def test_every_class_group_kernel(top, merge):
+    """One launch across classes: the half-range shapes of orders up to
+    `top` form four launch groups (f or f and chi, WENO-5 or upwind-3), each
+    run by the kernel compiled for orders up to `top`, with a block per window
+    (merge 1) or persistent blocks (merge 2), under graph replay."""
+    import paper_1708_03249_amd as H
+    chans = _shapes(H.HALF_HERMITE, [q for q in HALF_ORDERS if q <= top])
+    _run(chans, H.FP64, dict(merge_classes=merge, graph_steps=2), 1e-12,
+         f"class groups up to Q = {top}, merge {merge}")
